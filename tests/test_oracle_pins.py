@@ -1,0 +1,427 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code: brute force over odd subsets and
+codewords, the full LP relaxation solved by HiGHS, closed forms (Wagner's rule for a single
+parity check, Lemma 1), the paper's worked pseudocodeword, theorem invariants, and the
+block Newton system of Sec. IV-B.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth.channel import awgn_llr, bsc_llr, frame_seed
+from synth.codes import from_dense, irregular_code, regular_code
+from tests import refs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Algorithm 2 + Theorem 1
+def test_alg2_matches_bruteforce_and_theorem1(orc):
+    rng = np.random.Generator(np.random.PCG64(11))
+    cases = []
+    for d in range(2, 9):
+        for _ in range(300):
+            cases.append(rng.random(d))
+        for _ in range(50):  # values on the grid {0, 1/4, 1/2, 3/4, 1}: ties and exact halves
+            cases.append(rng.integers(0, 5, size=d) / 4.0)
+        for _ in range(30):
+            cases.append(rng.integers(0, 2, size=d).astype(float))
+    for u in cases:
+        d = len(u)
+        lhs_all = {}
+        for V in refs.odd_subsets(d):
+            Vs = set(V)
+            lhs_all[V] = sum((1 - u[k]) if k in Vs else u[k] for k in range(d))
+        viol = [V for V, v in lhs_all.items() if v < 1 - 1e-6]
+        strict = [V for V, v in lhs_all.items() if v < 1]
+        assert len(strict) <= 1                         # Theorem 1
+        got, vmask, lhs = orc.find_cut(u)
+        Vgot = tuple(k for k in range(d) if (vmask >> k) & 1)
+        assert len(Vgot) % 2 == 1
+        assert abs(lhs - lhs_all[Vgot]) < 1e-12
+        assert lhs == pytest.approx(min(lhs_all.values()), abs=1e-12)   # V minimises the LHS
+        assert got == bool(viol)
+        if viol:
+            assert Vgot == viol[0]
+
+
+# ---------------------------------------------------------------- augmented form (Sec. IV-B)
+def _x_space(code, gamma, masks):
+    """Sign transform written from its definition: x_i = u_i if gamma_i >= 0 else 1 - u_i,
+    one slack per cut row; rows in ascending check order."""
+    rows = [j for j in range(code.m) if masks[j]]
+    p, n = len(rows), code.n
+    A = np.zeros((p, n + p))
+    b = np.zeros(p)
+    for r, j in enumerate(rows):
+        a, bb = refs.cut_row_u(code, j, int(masks[j]))
+        for i in range(n):
+            if gamma[i] < 0 and a[i] != 0:
+                bb -= a[i]
+                a[i] = -a[i]
+        A[r, :n] = a
+        A[r, n + r] = 1.0
+        b[r] = bb
+    c = np.concatenate([np.abs(gamma), np.zeros(p)])
+    return A, b, c
+
+
+def _random_masks(code, rng, frac=0.6):
+    masks = np.zeros(code.m, dtype=np.uint32)
+    for j in range(code.m):
+        if rng.random() < frac:
+            d = len(code.row(j))
+            V = rng.choice(d, size=rng.choice(np.arange(1, d + 1, 2)), replace=False)
+            masks[j] = sum(1 << int(k) for k in V)
+    return masks
+
+
+def test_sign_transform_exact(orc):
+    rng = np.random.Generator(np.random.PCG64(5))
+    code = regular_code(60)
+    for _ in range(20):
+        gamma = rng.standard_normal(code.n)
+        masks = _random_masks(code, rng)
+        A, b, c = orc.lp_dense(code, gamma, masks)
+        A2, b2, c2 = _x_space(code, gamma, masks)
+        assert np.array_equal(A, A2) and np.array_equal(b, b2) and np.array_equal(c, c2)
+        # dyadic u: the u-space slack of every cut equals b - A_std x exactly
+        u = rng.integers(0, 9, size=code.n) / 8.0
+        x = np.where(gamma >= 0, u, 1 - u)
+        rows = [j for j in range(code.m) if masks[j]]
+        for r, j in enumerate(rows):
+            a, bb = refs.cut_row_u(code, j, int(masks[j]))
+            assert bb - a @ u == b[r] - A[r, :code.n] @ x
+
+
+# ---------------------------------------------------------------- IPM on one LP (Sec. IV-B)
+def test_ipm_matches_highs_and_kkt(orc):
+    code = regular_code(96)
+    checked = 0
+    for f in range(12):
+        gamma = awgn_llr(code.n, 1.5, 0.5, frame_seed(21, 0, f))
+        res = orc.decode(code, gamma, trace=True)
+        for k in range(res.malp_iters):
+            masks = res.trace_mask[k]
+            rc, x, y, z, its = orc.ipm(code, gamma, masks)
+            assert rc == 0 and its < 100
+            A, b, c = _x_space(code, gamma, masks)
+            assert np.all(x > 0) and np.all(z > 0)
+            assert np.linalg.norm(A @ x - b) / (1 + np.linalg.norm(b)) < 1e-8
+            assert np.linalg.norm(A.T @ y + z - c) / (1 + np.linalg.norm(c)) < 1e-8
+            assert x @ z / (1 + abs(c @ x)) < 1e-8
+            u = np.where(gamma >= 0, x[:code.n], 1 - x[:code.n])
+            fun, _ = refs.cutset_lp(code, gamma, masks)
+            assert gamma @ u == pytest.approx(fun, rel=1e-6, abs=1e-6)
+            assert gamma @ u == pytest.approx(res.trace_obj[k], abs=1e-12)
+            checked += 1
+    assert checked > 20
+
+
+def test_newton_block_system(orc):
+    """(dx, dy, dz) solve the 3x3 block Newton system of Sec. IV-B."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    code = regular_code(60)
+    for _ in range(10):
+        gamma = rng.standard_normal(code.n)
+        masks = _random_masks(code, rng)
+        A, b, c = _x_space(code, gamma, masks)
+        p, q = A.shape
+        x = rng.uniform(0.1, 2, q)
+        z = rng.uniform(0.1, 2, q)
+        y = rng.standard_normal(p)
+        mu = 0.37
+        dx, dy, dz = orc.newton(code, gamma, masks, x, y, z, mu)
+        rb, rc, re = b - A @ x, c - A.T @ y - z, mu - x * z
+        assert np.allclose(A @ dx, rb, atol=1e-9)
+        assert np.allclose(A.T @ dy + dz, rc, atol=1e-9)
+        assert np.allclose(z * dx + x * dz, re, atol=1e-9)
+
+
+# ---------------------------------------------------------------- whole decoder
+def _frames(code, snrs, per, stream):
+    out = []
+    for si, s in enumerate(snrs):
+        for f in range(per):
+            out.append(awgn_llr(code.n, s, 1 - code.m / code.n, frame_seed(stream, si, f)))
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_malp_equals_full_lp_decoding(orc, mode):
+    """Theorem 2c: MALP reaches the LP-decoding optimum over the fundamental polytope."""
+    code = regular_code(96)
+    opts = orc.OracleOpts(malp_mode=mode)
+    for gamma in _frames(code, [1.0, 1.5, 2.5], 8, 31):
+        res = orc.decode(code, gamma, opts)
+        assert res.status == 0
+        fun, ustar = refs.feldman_lp(code, gamma)
+        assert res.objective == pytest.approx(fun, rel=1e-6, abs=1e-6)
+        assert np.abs(res.u - ustar).max() < 1e-5
+
+
+def test_malp_irregular_bsc_equals_full_lp(orc):
+    """The irregular ensemble and the BSC with the small continuous perturbation."""
+    code = irregular_code(256)
+    for f in range(10):
+        gamma = bsc_llr(code.n, 0.08, frame_seed(41, 0, f))
+        res = orc.decode(code, gamma)
+        fun, _ = refs.feldman_lp(code, gamma)
+        assert res.objective == pytest.approx(fun, rel=1e-6, abs=1e-6)
+
+
+def test_integral_output_is_ml_codeword(orc):
+    """ML certificate (Sec. II-B): an integral LP output is the ML codeword; the LP optimum
+    never exceeds the ML cost."""
+    n_int = 0
+    for n in (24, 28):
+        code = regular_code(n, no4=False)
+        H = code.dense()
+        for gamma in _frames(code, [0.5, 1.0, 2.0, 3.0], 10, 51):
+            res = orc.decode(code, gamma)
+            u_ml, c_ml, _, _ = refs.ml_decode(H, gamma)
+            assert res.objective <= c_ml + 1e-6
+            if res.flag == 1:
+                n_int += 1
+                assert np.array_equal(res.xhat, u_ml)
+                assert res.objective == pytest.approx(c_ml, abs=1e-6)
+    assert n_int > 20
+
+
+def test_single_parity_check_wagner(orc):
+    """m = 1 (Lemma 1: the check polytope is the codeword polytope): LP = ML = Wagner's rule."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    for d in (3, 6, 7, 8):
+        code = from_dense(np.ones((1, d), dtype=np.uint8))
+        for _ in range(40):
+            gamma = rng.standard_normal(d) * 2 + 0.3
+            hard = (gamma < 0).astype(np.uint8)
+            want = hard.copy()
+            if hard.sum() % 2:
+                k = int(np.argmin(np.abs(gamma)))
+                want[k] ^= 1
+            res = orc.decode(code, gamma)
+            assert res.flag == 1
+            assert np.array_equal(res.xhat, want)
+
+
+def test_hard_decision_codeword_solves_no_lp(orc):
+    code = regular_code(96)
+    rng = np.random.Generator(np.random.PCG64(8))
+    B = refs.gf2_nullspace(code.dense())
+    for _ in range(10):
+        cw = (rng.integers(0, 2, B.shape[0]) @ B) % 2
+        gamma = rng.uniform(0.5, 3, code.n) * np.where(cw == 1, -1.0, 1.0)
+        res = orc.decode(code, gamma)
+        assert res.malp_iters == 0 and res.flag == 1
+        assert np.array_equal(res.xhat, cw.astype(np.uint8))
+
+
+def test_high_snr_all_zero(orc):
+    code = regular_code(240)
+    for gamma in _frames(code, [6.0], 10, 61):
+        res = orc.decode(code, gamma)
+        assert res.flag == 1 and not res.xhat.any()
+
+
+def test_theorem_invariants(orc):
+    """Theorem 2a (box), 2b (strictly increasing cost), 2c (at most n LPs), Theorem 3 /
+    Corollary 3 (at most one cut per check, p <= m), Corollary 5 (at most m fractional
+    entries), the counting bound of Corollary 4 in its proved form (the LP solution differs
+    from the hard decision in at most as many places as there are tight parity inequalities,
+    hence at most m), and Theorem 4 (the flipped set of an integral output has no stopping set)."""
+    code = regular_code(96)
+    n_frac = n_int = 0
+    for gamma in _frames(code, [1.0, 1.5, 2.0], 20, 71):
+        res = orc.decode(code, gamma, trace=True)
+        assert res.status == 0
+        assert res.u.min() > -1e-5 and res.u.max() < 1 + 1e-5   # IPM accuracy
+        assert res.malp_iters <= code.n
+        assert np.all(np.diff(res.trace_obj) > -1e-7)
+        if res.malp_iters:
+            assert res.trace_p.max() <= code.m
+        hard = (gamma < 0).astype(float)
+        nfr = int(np.sum(np.minimum(res.u, 1 - res.u) > 1e-4))
+        assert nfr <= code.m
+        moved = int(np.sum(np.abs(res.u - hard) > 1e-4))
+        assert moved <= (res.p_final if res.malp_iters else 0) <= code.m
+        if res.flag == 1:
+            n_int += 1
+            flipped = res.xhat != hard.astype(np.uint8)
+            assert refs.peel(code, flipped)
+        else:
+            n_frac += 1
+    assert n_int > 10 and n_frac > 3
+
+
+def test_peeling_helper_matches_bruteforce():
+    code = regular_code(24, no4=False)
+    rng = np.random.Generator(np.random.PCG64(2))
+    for _ in range(200):
+        S = rng.random(code.n) < rng.uniform(0.1, 0.5)
+        assert refs.peel(code, S) == (not refs.has_stopping_set(code, S))
+
+
+def test_hamming743_pseudocodeword(orc):
+    """The (7,4,3) pseudocodeword printed after Corollary 5: exactly m = 3 fractional entries,
+    reached by LP decoding for a cost vector inside its normal cone."""
+    g = json.load(open(os.path.join(GOLDEN, "hamming743.json")))
+    code = from_dense(np.array(g["H"]))
+    f = np.array(g["pseudocodeword"])
+    for mode in (0, 1):
+        res = orc.decode(code, np.array(g["gamma"]), orc.OracleOpts(malp_mode=mode))
+        assert res.flag == 0
+        assert np.abs(res.u - f).max() < 1e-6
+        assert int(np.sum(np.abs(res.u - 0.5) < 1e-6)) == code.m == 3
+
+
+# ---------------------------------------------------------------- Algorithm 7 + levels
+def mts_scan(code, hascut, w):
+    """Algorithm 7 by exhaustive scan: every step takes the degree-1 column of largest
+    (float32 weight, -index) and eliminates its row. O(p q)."""
+    n, m = code.n, code.m
+    rows_of = {i: [] for i in range(n)}
+    for j in range(m):
+        if hascut[j]:
+            for i in code.row(j):
+                rows_of[int(i)].append(j)
+    for j in range(m):
+        if hascut[j]:
+            rows_of[n + j] = [j]
+    alive = {j for j in range(m) if hascut[j]}
+    chosen = set()
+    pair = np.full(m, -1, dtype=np.int32)
+    order = []
+    while alive:
+        best, bkey, brow = None, None, None
+        for c, rs in rows_of.items():
+            if c in chosen:
+                continue
+            live = [r for r in rs if r in alive]
+            if len(live) == 1:
+                key = (np.float32(w[c]), -c)
+                if bkey is None or key > bkey:
+                    best, bkey, brow = c, key, live[0]
+        pair[brow] = best
+        order.append(brow)
+        alive.discard(brow)
+        chosen.add(best)
+    return pair, np.array(order, dtype=np.int32)
+
+
+def _weights(rng, q, kind):
+    if kind == "ties":
+        return rng.integers(0, 4, q).astype(np.float32)
+    if kind == "spread":
+        return (10.0 ** rng.uniform(-8, 8, q)).astype(np.float32)
+    return rng.random(q).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "ties", "spread"])
+def test_mts_heap_equals_scan_and_is_triangular(orc, kind):
+    rng = np.random.Generator(np.random.PCG64(17))
+    for n in (48, 96, 150):
+        code = regular_code(n) if n >= 60 else regular_code(n, no4=False)
+        for _ in range(6):
+            hascut = (rng.random(code.m) < 0.8).astype(np.uint8)
+            w = _weights(rng, code.n + code.m, kind)
+            pair, order = orc.mts(code, hascut, w)
+            p2, o2 = mts_scan(code, hascut, w)
+            assert np.array_equal(pair, p2) and np.array_equal(order, o2)
+            p = int(hascut.sum())
+            assert len(order) == p and len(set(order.tolist())) == p
+            # A_M with rows in elimination order and columns in the same order is upper
+            # triangular with a nonzero diagonal (Algorithm 7)
+            H = code.dense()
+            cols = [int(pair[j]) for j in order]
+            for k, j in enumerate(order):
+                for l, c in enumerate(cols):
+                    nz = (c >= code.n and c - code.n == j) or (c < code.n and H[j, c])
+                    if l == k:
+                        assert nz
+                    elif l < k:
+                        assert not nz
+
+
+def test_mts_levels_are_longest_chains(orc):
+    rng = np.random.Generator(np.random.PCG64(23))
+    code = regular_code(120)
+    n = code.n
+    for _ in range(8):
+        hascut = (rng.random(code.m) < 0.75).astype(np.uint8)
+        w = _weights(rng, code.n + code.m, "spread")
+        pair, order = orc.mts(code, hascut, w)
+        lb, lf = orc.mts_levels(code, hascut, pair, order)
+        pairrow = {int(pair[j]): j for j in range(code.m) if pair[j] >= 0}
+        rows_of = {i: [j for j in range(code.m) if hascut[j] and i in code.row(j)] for i in range(n)}
+
+        def deps_b(j):
+            return [pairrow[int(i)] for i in code.row(j) if int(i) != pair[j] and int(i) in pairrow]
+
+        def deps_f(j):
+            c = int(pair[j])
+            return [] if c >= n else [r for r in rows_of[c] if r != j]
+
+        memo = {}
+
+        def depth(j, deps, tag):
+            if (tag, j) not in memo:
+                d = deps(j)
+                memo[(tag, j)] = 0 if not d else 1 + max(depth(k, deps, tag) for k in d)
+            return memo[(tag, j)]
+
+        for j in range(code.m):
+            if hascut[j]:
+                assert lb[j] == depth(j, deps_b, "b")
+                assert lf[j] == depth(j, deps_f, "f")
+            else:
+                assert lb[j] == -1 and lf[j] == -1
+
+
+# ---------------------------------------------------------------- PCG (Algorithm 4)
+def _lp_instance(orc, code, seed):
+    gamma = awgn_llr(code.n, 1.5, 0.5, frame_seed(seed, 0, 0))
+    res = orc.decode(code, gamma, trace=True)
+    masks = res.trace_mask[-1] if res.malp_iters else _random_masks(code, np.random.Generator(np.random.PCG64(seed)))
+    return gamma, masks
+
+
+def test_pcg_fp64_equals_cholesky(orc):
+    rng = np.random.Generator(np.random.PCG64(4))
+    code = regular_code(200)
+    for s in range(4):
+        gamma, masks = _lp_instance(orc, code, 80 + s)
+        d2 = rng.uniform(0.1, 10, code.n + code.m)
+        w = rng.standard_normal(code.m) * (masks != 0)
+        y_ref = orc.normal_solve(code, gamma, masks, d2, w)
+        for precond in (True, False):
+            y, it, res = orc.pcg(code, gamma, masks, d2, w, tol=1e-12, maxit=2000, precond=precond)
+            assert res[-1] <= 1e-12
+            assert np.abs(y - y_ref).max() <= 1e-9 * max(1, np.abs(y_ref).max())
+
+
+def test_pcg_exact_preconditioner_one_iteration(orc):
+    """When D^2 vanishes off the preconditioning set, M = Q and PCG stops after one step."""
+    rng = np.random.Generator(np.random.PCG64(6))
+    code = regular_code(120)
+    hits = 0
+    for s in range(10):
+        gamma, masks = _lp_instance(orc, code, 90 + s)
+        hascut = (masks != 0).astype(np.uint8)
+        w0 = rng.random(code.n + code.m).astype(np.float32)
+        pair, _ = orc.mts(code, hascut, w0)
+        inM = np.zeros(code.n + code.m, dtype=bool)
+        inM[pair[pair >= 0]] = True
+        d2 = np.where(inM, rng.uniform(0.5, 2, code.n + code.m), 0.0)
+        pair2, _ = orc.mts(code, hascut, d2.astype(np.float32))
+        if not np.array_equal(np.sort(pair2[pair2 >= 0]), np.sort(pair[pair >= 0])):
+            continue
+        hits += 1
+        w = rng.standard_normal(code.m) * hascut
+        y, it, res = orc.pcg(code, gamma, masks, d2, w, tol=1e-10, maxit=50)
+        assert it == 1 and res[-1] < 1e-10
+    assert hits >= 3
