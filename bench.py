@@ -1,0 +1,233 @@
+"""Benchmark: LP-decoded frames/s of the batched decoder on the (3,6)-regular n=1024 code.
+
+One step = one launch of the decoder over a batch of 512 frames (Eb/N0 1.5 / 2.0 / 2.5 dB,
+171/171/170 frames, FP32 LLRs, FP32 PCG with FP64 refinement): every step of the hot path
+(cut search, cut update, interior-point iterations, triangular-set search, PCG) runs inside
+that launch. Inputs are resident in device memory before timing starts.
+
+Prints one JSON line. Extra legs, each reported beside the main number:
+  plain_fp64   the same frames through lpdec_decode (FP64, one frame per launch, host
+               pointers), a bounded sample;
+  cpu_baseline the FP64 CPU oracle on the host cores, a time-bounded sample;
+  roofline     effective bandwidth of the decode kernel on its algorithmic bytes;
+  serving      (--serve) Poisson arrivals of mixed-length frames through lpdec_server.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, SNRS, SPLIT = 1024, (1.5, 2.0, 2.5), (171, 171, 170)
+HBM_PEAK_GBS = 8000.0
+
+
+def workload():
+    from synth.channel import batch_awgn
+    from synth.codes import regular_code
+    code = regular_code(N)
+    G = np.concatenate([batch_awgn(code.n, 0.5, s, k, stream=2024, snr_index=i)
+                        for i, (s, k) in enumerate(zip(SNRS, SPLIT))]).astype(np.float32)
+    return code, G
+
+
+def algorithmic_bytes(st, n):
+    """Bytes the method must move per frame: per PCG iteration 27p + 4q
+    (q = n + p, FP32 vectors), per interior-point iteration 120q (FP64 vector passes)."""
+    pcg_rows = st["pcg_rows"].astype(np.float64)
+    pcg_its = st["pcg_iters"].astype(np.float64)
+    ipm_cols = st["ipm_cols"].astype(np.float64)
+    return float(np.sum(27 * pcg_rows + 4 * (pcg_its * n + pcg_rows) + 120 * ipm_cols))
+
+
+def _oracle_worker(args):
+    code_spec, gamma = args
+    import oracle
+    from synth.codes import regular_code
+    code = regular_code(code_spec)
+    t = time.perf_counter()
+    r = oracle.decode(code, gamma)
+    return time.perf_counter() - t, r.xhat, r.flag, r.objective
+
+
+def cpu_baseline(G, budget_s=12.0):
+    from concurrent.futures import ProcessPoolExecutor, FIRST_COMPLETED, wait
+    import oracle
+    oracle.build(force=False)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(avail, 16))
+    done, t0 = [], time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        pending, nxt = {}, 0
+        while nxt < G.shape[0] and len(pending) < workers:
+            pending[ex.submit(_oracle_worker, (N, G[nxt].astype(np.float64)))] = nxt
+            nxt += 1
+        while pending:
+            fin, _ = wait(list(pending), return_when=FIRST_COMPLETED)
+            for f in fin:
+                k = pending.pop(f)
+                done.append((k, f.result()))
+                if nxt < G.shape[0] and time.perf_counter() - t0 < budget_s:
+                    pending[ex.submit(_oracle_worker, (N, G[nxt].astype(np.float64)))] = nxt
+                    nxt += 1
+    wall = time.perf_counter() - t0
+    return {"value": len(done) / wall, "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {len(done)} frames of the benchmark batch (n=1024, 1.5/2.0/2.5 dB), "
+                      f"{workers} worker processes, {wall:.1f} s wall",
+            "single_thread_s_per_frame": float(np.mean([d[1][0] for d in done]))}, done
+
+
+def plain_fp64(ctx, C, G, frames):
+    t0 = time.perf_counter()
+    res = []
+    for f in frames:
+        xh, flag, obj, st, _ = ctx.decode(C, G[f].astype(np.float64))
+        res.append((f, xh, flag, obj))
+    wall = time.perf_counter() - t0
+    return {"value": len(frames) / wall, "unit": "frames/s", "frames": len(frames),
+            "sample": "frames spread over the three Eb/N0 points, lpdec_decode (FP64, one frame per launch)"}, res
+
+
+def serving(ctx, seconds=20.0, qps=None, seed=5):
+    """Poisson arrivals of frames from codes n in {256, 1024, 4096 (3,6); 8192 irregular},
+    Eb/N0 uniform in [1.5, 3.0] dB, through lpdec_server."""
+    from paper_0902_0657_amd import Code
+    from synth.channel import awgn_llr, frame_seed
+    from synth.codes import irregular_code, regular_code
+    codes = [regular_code(256), regular_code(1024), regular_code(4096), irregular_code(8192)]
+    Cs = [Code.from_synth(ctx, c) for c in codes]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
+    qps = qps or 400.0
+    t0 = time.perf_counter()
+    tickets, t_next, k = [], t0, 0
+    while time.perf_counter() - t0 < seconds:
+        now = time.perf_counter()
+        while t_next <= now:
+            ci = int(rng.integers(0, 4))
+            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(77, ci, k))
+            tickets.append((srv.submit(Cs[ci], g), codes[ci].n))
+            k += 1
+            t_next += rng.exponential(1.0 / qps)
+        time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
+    srv.drain()
+    wall = time.perf_counter() - t0
+    lat = []
+    for t, n in tickets:
+        r = srv.poll(t, n)
+        lat.append(r[3])
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": len(lat), "offered_qps": qps, "frames_per_s": len(lat) / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: frames are independent LPs and the "
+                                   "multi-GPU form is a per-frame shard with no exchange (see DESIGN.md); "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_0902_0657_amd import Code, Context, _lib, stats_table
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_0902_0657_amd import build as B
+        B.build()
+    code, G = workload()
+    ctx = Context(0)
+    if args.block:
+        ctx.set_option("BLOCK", args.block)
+    C = Code.from_synth(ctx, code)
+    dev = torch.device("cuda:0")
+    g = torch.as_tensor(G, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = ctx.decode_batch(C, g)
+    for _ in range(max(0, args.warmup - 1)):
+        ctx.decode_batch(C, g, out=out)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        ctx.decode_batch(C, g, out=out)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    total_s = float(step_ms.sum()) / 1e3
+    nf = G.shape[0]
+    value = nf * args.steps / total_s
+    st = stats_table(out["stats"])
+    flags = out["flag"].cpu().numpy()
+    xhat = out["xhat"].cpu().numpy()
+    objs = out["obj"].cpu().numpy()
+    alg = algorithmic_bytes(st, code.n)
+    kern_s = float(step_ms.mean()) / 1e3
+    achieved = alg / kern_s / 1e9
+    res = {
+        "metric": "LP-decoded frames/s at n=1024 (3,6) + p50/p99 latency, vs plain FP64 GPU",
+        "value": value, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": float(step_ms.mean()), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 PCG / f64 IPM", "data": "synthetic",
+        "config": {"workload": "(3,6)-regular LDPC n=1024 m=512, AWGN Eb/N0 1.5/2.0/2.5 dB "
+                               "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
+                               "FP32 PCG tol 1e-6 + FP64 refinement",
+                   "global_batch": nf, "parallelism": "one workgroup per frame"},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "note": "batch mode: every frame of a launch completes with the launch"},
+        "wall_s_timed": wall,
+        "decode_stats": {"flags": {str(k): int(v) for k, v in zip(*np.unique(flags, return_counts=True))},
+                         "mean_malp_iters": float(st["malp_iters"].mean()),
+                         "mean_ipm_iters": float(st["ipm_iters"].mean()),
+                         "mean_pcg_iters": float(st["pcg_iters"].mean()),
+                         "mean_pcg_per_newton": float(st["pcg_iters"].sum() / max(1, st["ipm_iters"].sum())),
+                         "max_p": int(st["p_max"].max()), "max_levels": int(st["max_levels"].max()),
+                         "mean_mts_rounds_per_ipm": float(st["mts_rounds"].sum() / max(1, st["ipm_iters"].sum())),
+                         "ref_rounds": int(st["ref_rounds"].sum())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "lpdec_main<float, LDS, DECODE>",
+                     "algorithmic_bytes_per_launch": alg, "kernel_ms": kern_s * 1e3},
+    }
+    plain_res, cpu_res = None, None
+    if not args.no_plain:
+        frames = [0, 1, 2, 3, 171, 172, 173, 174, 342, 343, 344, 345]
+        pf, plain_res = plain_fp64(ctx, C, G, frames)
+        res["plain_fp64"] = pf
+        res["speedup_vs_plain"] = value / pf["value"]
+        mism = [f for f, xh, fl, ob in plain_res if not (np.array_equal(xh, xhat[f]) and fl == flags[f])]
+        res["plain_fp64"]["mismatch_vs_batch"] = len(mism)
+    if not args.no_cpu:
+        cb, done = cpu_baseline(G)
+        res["cpu_baseline"] = cb
+        mism = [k for k, (t, xh, fl, ob) in done
+                if not (np.array_equal(xh, xhat[k]) and fl == flags[k]
+                        and abs(ob - objs[k]) <= 1e-6 * max(1.0, abs(ob)))]
+        res["parity_sample"] = {"frames": len(done), "mismatches": len(mism)}
+    if args.serve:
+        res["serving"] = serving(ctx)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,749 @@
+// Host side of the C ABI declared in include/lpdec.h: contexts, codes, options, device
+// workspaces, launches, and the continuous-batching server.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lpdec_common.hpp"
+#include "lpdec_launch.hpp"
+
+using lpdec::Args;
+using lpdec::Plan;
+
+namespace {
+
+struct Workspace {
+    char *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+hipError_t ws_ensure(Workspace &w, size_t bytes)
+{
+    if (bytes <= w.bytes) return hipSuccess;
+    if (w.ptr) {
+        hipError_t e = hipFree(w.ptr);
+        if (e != hipSuccess) return e;
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    hipError_t e = hipMalloc((void **)&w.ptr, want);
+    if (e != hipSuccess) { w.ptr = nullptr; return e; }
+    w.bytes = want;
+    return hipSuccess;
+}
+
+void ws_free(Workspace &w)
+{
+    if (w.ptr) (void)hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
+}
+
+}  // namespace
+
+struct lpdec_ctx {
+    int device = 0;
+    lpdec::Opts opts{};
+    int precision = -1;   // -1: per call default
+    int block = 0;        // 0: automatic
+    int lds_limit = 65536;
+    std::string err;
+    Workspace ws;
+};
+
+struct lpdec_code {
+    lpdec_ctx *ctx = nullptr;
+    int m = 0, n = 0, E = 0, dcmax = 0, dvmax = 0;
+    int *d_rowptr = nullptr, *d_col = nullptr, *d_colptr = nullptr, *d_vlist = nullptr;
+    std::vector<int> rowptr, col;
+};
+
+namespace {
+
+lpdec_status fail(const lpdec_ctx *ctx, lpdec_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        const_cast<lpdec_ctx *>(ctx)->err = buf;
+    }
+    return st;
+}
+
+lpdec_status hipfail(const lpdec_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? LPDEC_ENOMEM : LPDEC_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+void default_opts(lpdec::Opts &o)
+{
+    o.malp_mode = 0;
+    o.malp_max = 200;
+    o.ipm_max = 100;
+    o.pcg_maxit = 500;
+    o.ref_max = 3;
+    o.precond = 1;
+    o.tau_viol = 1e-4;
+    o.tau_act = 1e-4;
+    o.tau_int = 1e-4;
+    o.eps = 1e-8;
+    o.sigma = 0.1;
+    o.eta = 0.9995;
+    o.pcg_tol = 1e-6;
+    o.ref_tol = 1e-10;
+    o.xi_tol = 0.1;
+}
+
+lpdec::CodeView view(const lpdec_code *c)
+{
+    lpdec::CodeView v;
+    v.m = c->m; v.n = c->n; v.E = c->E;
+    v.rowptr = c->d_rowptr; v.col = c->d_col; v.colptr = c->d_colptr; v.vlist = c->d_vlist;
+    return v;
+}
+
+int auto_block(const lpdec_code *c)
+{
+    // enough lanes that one pass over the columns needs few iterations, without making the
+    // per-level barriers of the triangular solves wider than the work in a level
+    const int q = c->n + c->m;
+    if (q <= 800) return 128;
+    if (q <= 3200) return 256;
+    if (q <= 8000) return 512;
+    return 1024;
+}
+
+// Fills the launch geometry and workspace of Args; launches one workgroup per frame.
+lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, Workspace &ws,
+                    hipStream_t stream)
+{
+    if (a.nframes <= 0) return LPDEC_OK;
+    a.code = view(code);
+    a.o = ctx->opts;
+    a.plan = lpdec::make_plan(code->m, code->n, pt64 ? 8 : 4);
+    const size_t lds_need = a.plan.hot_bytes;
+    const size_t lds_avail = (size_t)ctx->lds_limit - lpdec::static_lds_bytes() - 256;
+    a.hot_in_lds = lds_need <= lds_avail;
+    a.hot_stride = a.hot_in_lds ? 0 : lpdec::lp_align(a.plan.hot_bytes + 255) & ~(size_t)255;
+    a.cold_stride = (a.plan.cold_bytes + 255) & ~(size_t)255;
+    const size_t per = a.hot_stride + a.cold_stride;
+    hipError_t e = ws_ensure(ws, per * (size_t)a.nframes);
+    if (e != hipSuccess) return hipfail(ctx, e, "workspace allocation");
+    a.cold_ws = ws.ptr;
+    a.hot_ws = ws.ptr + a.cold_stride * (size_t)a.nframes;
+    int block = ctx->block > 0 ? ctx->block : auto_block(code);
+    e = lpdec::launch_main(a, pt64, block, a.hot_in_lds ? lds_need : 0, stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "kernel launch");
+    return LPDEC_OK;
+}
+
+int precision_for(const lpdec_ctx *ctx, int call_default) { return ctx->precision >= 0 ? ctx->precision : call_default; }
+
+lpdec_status check_common(lpdec_ctx *ctx, const lpdec_code *code, int nframes)
+{
+    if (!ctx) return LPDEC_EINVAL;
+    if (!code || code->ctx != ctx) return fail(ctx, LPDEC_EINVAL, "code is null or belongs to another context");
+    if (nframes < 0) return fail(ctx, LPDEC_EINVAL, "nframes < 0");
+    ctx->err.clear();
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    return LPDEC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ context
+extern "C" lpdec_status lpdec_ctx_create(int device, lpdec_ctx **out)
+{
+    if (!out) return LPDEC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LPDEC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LPDEC_EDEVICE;
+    auto *c = new (std::nothrow) lpdec_ctx();
+    if (!c) return LPDEC_ENOMEM;
+    c->device = device;
+    default_opts(c->opts);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->lds_limit = lds;
+    *out = c;
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_ctx_destroy(lpdec_ctx *ctx)
+{
+    if (!ctx) return LPDEC_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ws_free(ctx->ws);
+    delete ctx;
+    return LPDEC_OK;
+}
+
+extern "C" const char *lpdec_last_error(const lpdec_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
+{
+    if (!ctx) return LPDEC_EINVAL;
+    lpdec::Opts &o = ctx->opts;
+    auto ipos = [&](int lo) { return v >= lo && v <= 1e9 && v == (double)(long long)v; };
+    switch (key) {
+    case LPDEC_OPT_MALP_MODE: if (v != 0 && v != 1) break; o.malp_mode = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_PRECISION: if (v != -1 && v != 0 && v != 1) break; ctx->precision = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_TAU_VIOL: if (!(v >= 0 && v < 1)) break; o.tau_viol = v; return LPDEC_OK;
+    case LPDEC_OPT_TAU_ACT: if (!(v >= 0 && v < 1)) break; o.tau_act = v; return LPDEC_OK;
+    case LPDEC_OPT_TAU_INT: if (!(v >= 0 && v < 0.5)) break; o.tau_int = v; return LPDEC_OK;
+    case LPDEC_OPT_IPM_EPS: if (!(v > 0 && v < 1)) break; o.eps = v; return LPDEC_OK;
+    case LPDEC_OPT_SIGMA: if (!(v > 0 && v < 1)) break; o.sigma = v; return LPDEC_OK;
+    case LPDEC_OPT_ETA: if (!(v > 0 && v < 1)) break; o.eta = v; return LPDEC_OK;
+    case LPDEC_OPT_PCG_TOL: if (!(v > 0 && v < 1)) break; o.pcg_tol = v; return LPDEC_OK;
+    case LPDEC_OPT_PCG_MAXIT: if (!ipos(1)) break; o.pcg_maxit = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_REF_TOL: if (!(v > 0 && v < 1)) break; o.ref_tol = v; return LPDEC_OK;
+    case LPDEC_OPT_REF_MAX: if (!ipos(0)) break; o.ref_max = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_IPM_MAX: if (!ipos(1)) break; o.ipm_max = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_MALP_MAX: if (!ipos(1)) break; o.malp_max = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_BLOCK:
+        if (!(v == 0 || (ipos(64) && v <= 1024 && ((int)v % 64) == 0))) break;
+        ctx->block = (int)v;
+        return LPDEC_OK;
+    case LPDEC_OPT_PRECOND: if (v != 0 && v != 1) break; o.precond = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
+    default: return fail(ctx, LPDEC_EINVAL, "unknown option key %d", key);
+    }
+    return fail(ctx, LPDEC_EINVAL, "bad value %g for option %d", v, key);
+}
+
+extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *v)
+{
+    if (!ctx || !v) return LPDEC_EINVAL;
+    const lpdec::Opts &o = ctx->opts;
+    switch (key) {
+    case LPDEC_OPT_MALP_MODE: *v = o.malp_mode; break;
+    case LPDEC_OPT_PRECISION: *v = ctx->precision; break;
+    case LPDEC_OPT_TAU_VIOL: *v = o.tau_viol; break;
+    case LPDEC_OPT_TAU_ACT: *v = o.tau_act; break;
+    case LPDEC_OPT_TAU_INT: *v = o.tau_int; break;
+    case LPDEC_OPT_IPM_EPS: *v = o.eps; break;
+    case LPDEC_OPT_SIGMA: *v = o.sigma; break;
+    case LPDEC_OPT_ETA: *v = o.eta; break;
+    case LPDEC_OPT_PCG_TOL: *v = o.pcg_tol; break;
+    case LPDEC_OPT_PCG_MAXIT: *v = o.pcg_maxit; break;
+    case LPDEC_OPT_REF_TOL: *v = o.ref_tol; break;
+    case LPDEC_OPT_REF_MAX: *v = o.ref_max; break;
+    case LPDEC_OPT_IPM_MAX: *v = o.ipm_max; break;
+    case LPDEC_OPT_MALP_MAX: *v = o.malp_max; break;
+    case LPDEC_OPT_BLOCK: *v = ctx->block; break;
+    case LPDEC_OPT_PRECOND: *v = o.precond; break;
+    case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
+    default: return LPDEC_EINVAL;
+    }
+    return LPDEC_OK;
+}
+
+// ------------------------------------------------------------------------------ code
+extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, const int32_t *rowptr,
+                                          const int32_t *col, lpdec_code **out)
+{
+    if (!ctx) return LPDEC_EINVAL;
+    if (!out || !rowptr || !col) return fail(ctx, LPDEC_EINVAL, "null argument");
+    *out = nullptr;
+    if (m <= 0 || n <= 0 || m >= (1 << 26)) return fail(ctx, LPDEC_EINVAL, "bad sizes m=%d n=%d", m, n);
+    if (rowptr[0] != 0) return fail(ctx, LPDEC_EINVAL, "rowptr[0] != 0");
+    int dcmax = 0;
+    for (int j = 0; j < m; ++j) {
+        const int d = rowptr[j + 1] - rowptr[j];
+        if (d < 1 || d > 32) return fail(ctx, LPDEC_EINVAL, "row %d has degree %d (need 1..32)", j, d);
+        dcmax = std::max(dcmax, d);
+        for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n) return fail(ctx, LPDEC_EINVAL, "row %d: column %d out of range", j, col[e]);
+            if (e > rowptr[j] && col[e] <= col[e - 1])
+                return fail(ctx, LPDEC_EINVAL, "row %d: columns not strictly increasing", j);
+        }
+    }
+    const int E = rowptr[m];
+    auto *c = new (std::nothrow) lpdec_code();
+    if (!c) return LPDEC_ENOMEM;
+    c->ctx = ctx; c->m = m; c->n = n; c->E = E; c->dcmax = dcmax;
+    c->rowptr.assign(rowptr, rowptr + m + 1);
+    c->col.assign(col, col + E);
+    std::vector<int> colptr(n + 1, 0), vlist(E);
+    for (int e = 0; e < E; ++e) colptr[col[e] + 1]++;
+    for (int i = 0; i < n; ++i) colptr[i + 1] += colptr[i];
+    for (int i = 0; i < n; ++i) c->dvmax = std::max(c->dvmax, colptr[i + 1] - colptr[i]);
+    std::vector<int> fill(colptr.begin(), colptr.end() - 1);
+    for (int j = 0; j < m; ++j)
+        for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) vlist[fill[col[e]]++] = (j << 5) | (e - rowptr[j]);
+    hipError_t er = hipSetDevice(ctx->device);
+    if (er == hipSuccess) er = hipMalloc((void **)&c->d_rowptr, sizeof(int) * (m + 1));
+    if (er == hipSuccess) er = hipMalloc((void **)&c->d_col, sizeof(int) * E);
+    if (er == hipSuccess) er = hipMalloc((void **)&c->d_colptr, sizeof(int) * (n + 1));
+    if (er == hipSuccess) er = hipMalloc((void **)&c->d_vlist, sizeof(int) * E);
+    if (er == hipSuccess) er = hipMemcpy(c->d_rowptr, rowptr, sizeof(int) * (m + 1), hipMemcpyHostToDevice);
+    if (er == hipSuccess) er = hipMemcpy(c->d_col, col, sizeof(int) * E, hipMemcpyHostToDevice);
+    if (er == hipSuccess) er = hipMemcpy(c->d_colptr, colptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    if (er == hipSuccess) er = hipMemcpy(c->d_vlist, vlist.data(), sizeof(int) * E, hipMemcpyHostToDevice);
+    if (er != hipSuccess) {
+        lpdec_code_destroy(c);
+        return hipfail(ctx, er, "code upload");
+    }
+    *out = c;
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_code_destroy(lpdec_code *c)
+{
+    if (!c) return LPDEC_EINVAL;
+    if (c->ctx) (void)hipSetDevice(c->ctx->device);
+    if (c->d_rowptr) (void)hipFree(c->d_rowptr);
+    if (c->d_col) (void)hipFree(c->d_col);
+    if (c->d_colptr) (void)hipFree(c->d_colptr);
+    if (c->d_vlist) (void)hipFree(c->d_vlist);
+    delete c;
+    return LPDEC_OK;
+}
+
+// ------------------------------------------------------------------------------ decoding
+static lpdec_status decode_batch_impl(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                      const void *gamma, int32_t gdt, uint8_t *xhat, int32_t *flag,
+                                      double *obj, lpdec_stats *stats, double *u, uint32_t *trace,
+                                      int32_t trace_cap, int pt64, Workspace &ws, hipStream_t stream)
+{
+    if (nframes > 0 && (!gamma || !xhat || !flag)) return fail(ctx, LPDEC_EINVAL, "null gamma/xhat/flag");
+    if (gdt != 0 && gdt != 1) return fail(ctx, LPDEC_EINVAL, "gamma_dtype must be 0 (f32) or 1 (f64)");
+    Args a{};
+    a.nframes = nframes;
+    a.mode = lpdec::MODE_DECODE;
+    a.gamma = gamma;
+    a.gamma_f64 = gdt;
+    a.xhat = xhat; a.flag = flag; a.obj = obj; a.stats = stats; a.u_out = u;
+    a.trace = trace; a.trace_cap = trace ? trace_cap : 0;
+    return launch(ctx, code, a, pt64, ws, stream);
+}
+
+extern "C" lpdec_status lpdec_decode_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                           const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
+                                           int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,
+                                           double *u_dev, void *stream)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    return decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev,
+                             stats_dev, u_dev, nullptr, 0, precision_for(ctx, 0), ctx->ws, (hipStream_t)stream);
+}
+
+extern "C" lpdec_status lpdec_decode_batch_trace(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                                 const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
+                                                 int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,
+                                                 double *u_dev, uint32_t *trace_dev, int32_t trace_cap)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (!trace_dev || trace_cap <= 0) return fail(ctx, LPDEC_EINVAL, "trace buffer required");
+    st = decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev, stats_dev,
+                           u_dev, trace_dev, trace_cap, precision_for(ctx, 0), ctx->ws, nullptr);
+    if (st) return st;
+    hipError_t e = hipDeviceSynchronize();
+    return e == hipSuccess ? LPDEC_OK : hipfail(ctx, e, "decode");
+}
+
+extern "C" lpdec_status lpdec_decode(lpdec_ctx *ctx, const lpdec_code *code, const double *gamma, uint8_t *xhat,
+                                     int32_t *flag, double *objective, lpdec_stats *stats, double *u)
+{
+    lpdec_status st = check_common(ctx, code, 1);
+    if (st) return st;
+    if (!gamma || !xhat || !flag) return fail(ctx, LPDEC_EINVAL, "null gamma/xhat/flag");
+    const int n = code->n;
+    // one device block holding gamma and every output of the frame
+    struct Dev { double obj; lpdec_stats st; int32_t flag; };
+    const size_t off_g = 0, off_u = lpdec::lp_align(8 * (size_t)n), off_x = off_u + lpdec::lp_align(8 * (size_t)n);
+    const size_t off_d = off_x + lpdec::lp_align((size_t)n), total = off_d + sizeof(Dev);
+    char *buf = nullptr;
+    hipError_t e = hipMalloc((void **)&buf, total);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipMalloc");
+    Dev *dv = (Dev *)(buf + off_d);
+    e = hipMemcpy(buf + off_g, gamma, 8 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        st = decode_batch_impl(ctx, code, 1, buf + off_g, 1, (uint8_t *)(buf + off_x), &dv->flag, &dv->obj,
+                               &dv->st, (double *)(buf + off_u), nullptr, 0, precision_for(ctx, 1), ctx->ws, nullptr);
+        if (st) { (void)hipFree(buf); return st; }
+        e = hipDeviceSynchronize();
+    }
+    Dev h;
+    if (e == hipSuccess) e = hipMemcpy(xhat, buf + off_x, n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && u) e = hipMemcpy(u, buf + off_u, 8 * (size_t)n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&h, dv, sizeof(Dev), hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hipfail(ctx, e, "decode");
+    *flag = h.flag;
+    if (objective) *objective = h.obj;
+    if (stats) *stats = h.st;
+    return LPDEC_OK;
+}
+
+// ------------------------------------------------------------------------------ steps
+static lpdec_status run_sync(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64)
+{
+    lpdec_status st = launch(ctx, code, a, pt64, ctx->ws, nullptr);
+    if (st) return st;
+    hipError_t e = hipDeviceSynchronize();
+    return e == hipSuccess ? LPDEC_OK : hipfail(ctx, e, "kernel");
+}
+
+extern "C" lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                               const double *u_dev, uint32_t *vmask_dev, uint8_t *viol_dev,
+                                               double *lhs_dev)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes > 0 && (!u_dev || !vmask_dev || !viol_dev)) return fail(ctx, LPDEC_EINVAL, "null argument");
+    Args a{};
+    a.nframes = nframes; a.mode = lpdec::MODE_CUTS;
+    a.vec_in = u_dev; a.u32_out = vmask_dev; a.u8_out = viol_dev; a.vec_out = lhs_dev;
+    return run_sync(ctx, code, a, 1);
+}
+
+extern "C" lpdec_status lpdec_mts_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                        const uint8_t *hascut_dev, const float *w_dev, int32_t *pair_dev,
+                                        int32_t *lev_b_dev, int32_t *lev_f_dev, int32_t *rounds_dev)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes > 0 && (!hascut_dev || !w_dev || !pair_dev || !lev_b_dev || !lev_f_dev))
+        return fail(ctx, LPDEC_EINVAL, "null argument");
+    Args a{};
+    a.nframes = nframes; a.mode = lpdec::MODE_MTS;
+    a.hascut_in = hascut_dev; a.w_in = w_dev;
+    a.i_out = pair_dev; a.i_out2 = lev_b_dev; a.i_out3 = lev_f_dev; a.flag = rounds_dev;
+    return run_sync(ctx, code, a, 0);
+}
+
+extern "C" lpdec_status lpdec_normal_matvec_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                                  const uint32_t *vmask_dev, const double *gamma_dev,
+                                                  const double *d2_dev, const double *h_dev, double *l_dev,
+                                                  int32_t precision)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes > 0 && (!vmask_dev || !gamma_dev || !d2_dev || !h_dev || !l_dev))
+        return fail(ctx, LPDEC_EINVAL, "null argument");
+    if (precision != 0 && precision != 1) return fail(ctx, LPDEC_EINVAL, "precision must be 0 or 1");
+    Args a{};
+    a.nframes = nframes; a.mode = lpdec::MODE_MATVEC;
+    a.vmask_in = vmask_dev; a.gamma = gamma_dev; a.gamma_f64 = 1; a.d2_in = d2_dev; a.vec_in = h_dev;
+    a.vec_out = l_dev;
+    return run_sync(ctx, code, a, precision);
+}
+
+extern "C" lpdec_status lpdec_newton_solve_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                                 const uint32_t *vmask_dev, const double *gamma_dev,
+                                                 const double *d2_dev, const double *w_dev, double *y_dev,
+                                                 int32_t *iters_dev, double *resid_dev, int32_t precision)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes > 0 && (!vmask_dev || !gamma_dev || !d2_dev || !w_dev || !y_dev))
+        return fail(ctx, LPDEC_EINVAL, "null argument");
+    if (precision != 0 && precision != 1) return fail(ctx, LPDEC_EINVAL, "precision must be 0 or 1");
+    Args a{};
+    a.nframes = nframes; a.mode = lpdec::MODE_SOLVE;
+    a.vmask_in = vmask_dev; a.gamma = gamma_dev; a.gamma_f64 = 1; a.d2_in = d2_dev; a.vec_in = w_dev;
+    a.vec_out = y_dev; a.i_out = iters_dev; a.d_out = resid_dev;
+    return run_sync(ctx, code, a, precision);
+}
+
+extern "C" lpdec_status lpdec_ipm_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                        const uint32_t *vmask_dev, const double *gamma_dev, double *x_dev,
+                                        double *y_dev, double *z_dev, int32_t *iters_dev, int32_t *status_dev,
+                                        int32_t precision)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes > 0 && (!vmask_dev || !gamma_dev || !x_dev || !y_dev || !z_dev || !iters_dev || !status_dev))
+        return fail(ctx, LPDEC_EINVAL, "null argument");
+    if (precision != 0 && precision != 1) return fail(ctx, LPDEC_EINVAL, "precision must be 0 or 1");
+    Args a{};
+    a.nframes = nframes; a.mode = lpdec::MODE_IPM;
+    a.vmask_in = vmask_dev; a.gamma = gamma_dev; a.gamma_f64 = 1;
+    a.x_out = x_dev; a.z_out = z_dev; a.vec_out = y_dev; a.i_out = iters_dev; a.i_out2 = status_dev;
+    return run_sync(ctx, code, a, precision);
+}
+
+// ------------------------------------------------------------------------------ serving
+// Continuous batching. Submitted frames wait in a host queue. A scheduler thread forms a
+// wave from the queue head whenever one of its streams is idle: it takes frames (of one code
+// per wave) while the wave's device footprint fits in the free part of the HBM budget and
+// the slots in flight stay under max_slots, copies their gamma to the wave's device buffer,
+// launches the decode kernel on that stream and records an event. Waves on different
+// streams overlap on the device; a finished wave's results are copied back and its memory
+// and slots are released, so frames that arrived meanwhile are admitted.
+namespace {
+
+struct Request {
+    uint64_t ticket;
+    const lpdec_code *code;
+    std::vector<double> gamma;
+    std::chrono::steady_clock::time_point t_submit;
+};
+
+struct Result {
+    std::vector<uint8_t> xhat;
+    int32_t flag = 0;
+    double obj = 0.0;
+    double latency = 0.0;
+};
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Workspace ws;                 // kernel workspace of this lane
+    Workspace io;                 // gamma in, results out
+    std::vector<Request> wave;    // frames in flight on this lane
+    size_t footprint = 0;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct lpdec_server {
+    lpdec_ctx *ctx = nullptr;
+    size_t budget = 0;
+    int max_slots = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::map<uint64_t, Result> results;
+    std::map<uint64_t, int> pending;   // ticket -> 1 while queued or running
+    uint64_t next_ticket = 1;
+    std::vector<Lane> lanes;
+    size_t in_use = 0;
+    int slots_in_use = 0;
+    bool stop = false;
+    std::thread worker;
+    std::string err;
+};
+
+namespace {
+
+size_t frame_footprint(const lpdec_code *c, int pt64)
+{
+    Plan p = lpdec::make_plan(c->m, c->n, pt64 ? 8 : 4);
+    // cold arena + hot arena (counted even when it lives in LDS) + gamma + outputs
+    return p.cold_bytes + p.hot_bytes + 8 * (size_t)c->n + (size_t)c->n + 64;
+}
+
+void server_loop(lpdec_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    const int pt64 = precision_for(s->ctx, 0);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        // retire finished waves
+        bool progressed = false;
+        for (auto &L : s->lanes) {
+            if (!L.busy) continue;
+            if (hipEventQuery(L.done) != hipSuccess) continue;
+            const auto now = std::chrono::steady_clock::now();
+            const int nf = (int)L.wave.size();
+            const int n = L.wave[0].code->n;
+            std::vector<uint8_t> xh((size_t)nf * n);
+            std::vector<int32_t> fl(nf);
+            std::vector<double> ob(nf);
+            char *base = L.io.ptr;
+            const size_t off_x = lpdec::lp_align(8 * (size_t)nf * n);
+            const size_t off_f = off_x + lpdec::lp_align((size_t)nf * n);
+            const size_t off_o = off_f + lpdec::lp_align(4 * (size_t)nf);
+            hipError_t e = hipMemcpy(xh.data(), base + off_x, xh.size(), hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(fl.data(), base + off_f, 4 * (size_t)nf, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(ob.data(), base + off_o, 8 * (size_t)nf, hipMemcpyDeviceToHost);
+            for (int k = 0; k < nf; ++k) {
+                Result r;
+                r.xhat.assign(xh.begin() + (size_t)k * n, xh.begin() + (size_t)(k + 1) * n);
+                r.flag = e == hipSuccess ? fl[k] : LPDEC_FLAG_NONFINITE;
+                r.obj = ob[k];
+                r.latency = std::chrono::duration<double>(now - L.wave[k].t_submit).count();
+                s->results[L.wave[k].ticket] = std::move(r);
+                s->pending.erase(L.wave[k].ticket);
+            }
+            s->in_use -= L.footprint;
+            s->slots_in_use -= nf;
+            L.wave.clear();
+            L.busy = false;
+            progressed = true;
+        }
+        if (progressed) s->cv_done.notify_all();
+        // admit a new wave on every idle lane while the queue head fits
+        for (auto &L : s->lanes) {
+            if (L.busy || s->queue.empty()) continue;
+            const lpdec_code *code = s->queue.front().code;
+            const size_t fp = frame_footprint(code, pt64);
+            int nf = 0;
+            size_t need = 0;
+            for (auto it = s->queue.begin(); it != s->queue.end() && it->code == code; ++it) {
+                if (s->slots_in_use + nf + 1 > s->max_slots) break;
+                if (s->in_use + need + fp > s->budget) break;
+                need += fp;
+                ++nf;
+            }
+            if (nf == 0) break;
+            for (int k = 0; k < nf; ++k) { L.wave.push_back(std::move(s->queue.front())); s->queue.pop_front(); }
+            const int n = code->n;
+            const size_t off_x = lpdec::lp_align(8 * (size_t)nf * n);
+            const size_t off_f = off_x + lpdec::lp_align((size_t)nf * n);
+            const size_t off_o = off_f + lpdec::lp_align(4 * (size_t)nf);
+            const size_t io_bytes = off_o + 8 * (size_t)nf;
+            std::vector<double> g((size_t)nf * n);
+            for (int k = 0; k < nf; ++k) std::copy(L.wave[k].gamma.begin(), L.wave[k].gamma.end(), g.begin() + (size_t)k * n);
+            hipError_t e = ws_ensure(L.io, io_bytes);
+            if (e == hipSuccess) e = hipMemcpyAsync(L.io.ptr, g.data(), 8 * g.size(), hipMemcpyHostToDevice, L.stream);
+            lpdec_status st = LPDEC_EDEVICE;
+            if (e == hipSuccess) {
+                // the stream's previous use of this gamma buffer is over: the copy is ordered
+                // before the kernel on the same stream; synchronise the copy so g can go
+                e = hipStreamSynchronize(L.stream);
+                st = e == hipSuccess
+                         ? decode_batch_impl(s->ctx, code, nf, L.io.ptr, 1, (uint8_t *)(L.io.ptr + off_x),
+                                             (int32_t *)(L.io.ptr + off_f), (double *)(L.io.ptr + off_o),
+                                             nullptr, nullptr, nullptr, 0, pt64, L.ws, L.stream)
+                         : LPDEC_EDEVICE;
+            }
+            if (st == LPDEC_OK) e = hipEventRecord(L.done, L.stream);
+            if (st != LPDEC_OK || e != hipSuccess) {
+                // report the failure on every frame of the wave
+                for (auto &r : L.wave) {
+                    Result res;
+                    res.xhat.assign(n, 0);
+                    res.flag = LPDEC_FLAG_NONFINITE;
+                    s->results[r.ticket] = std::move(res);
+                    s->pending.erase(r.ticket);
+                }
+                L.wave.clear();
+                s->err = "wave launch failed";
+                s->cv_done.notify_all();
+                continue;
+            }
+            L.footprint = need;
+            s->in_use += need;
+            s->slots_in_use += nf;
+            L.busy = true;
+        }
+        bool any_busy = false;
+        for (auto &L : s->lanes) any_busy |= L.busy;
+        if (s->stop && !any_busy && s->queue.empty()) break;
+        if (any_busy) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            lk.lock();
+        } else {
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" lpdec_status lpdec_server_create(lpdec_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots,
+                                            lpdec_server **out)
+{
+    if (!ctx || !out) return LPDEC_EINVAL;
+    if (max_slots <= 0 || hbm_budget_bytes == 0) return fail(ctx, LPDEC_EINVAL, "budget and max_slots must be > 0");
+    (void)hipSetDevice(ctx->device);
+    auto *s = new (std::nothrow) lpdec_server();
+    if (!s) return LPDEC_ENOMEM;
+    s->ctx = ctx;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->lanes.resize(4);
+    for (auto &L : s->lanes) {
+        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
+            lpdec_server_destroy(s);
+            return fail(ctx, LPDEC_EDEVICE, "stream creation failed");
+        }
+    }
+    s->worker = std::thread(server_loop, s);
+    *out = s;
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_server_submit(lpdec_server *s, const lpdec_code *code, const double *gamma,
+                                            uint64_t *ticket)
+{
+    if (!s || !code || !gamma || !ticket || code->ctx != s->ctx) return LPDEC_EINVAL;
+    Request r;
+    r.code = code;
+    r.gamma.assign(gamma, gamma + code->n);
+    r.t_submit = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return LPDEC_EINVAL;
+        if (frame_footprint(code, precision_for(s->ctx, 0)) > s->budget) return LPDEC_ENOMEM;
+        r.ticket = s->next_ticket++;
+        *ticket = r.ticket;
+        s->pending[r.ticket] = 1;
+        s->queue.push_back(std::move(r));
+    }
+    s->cv_work.notify_one();
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_server_poll(lpdec_server *s, uint64_t ticket, uint8_t *xhat, int32_t *flag,
+                                          double *objective, double *latency_s)
+{
+    if (!s) return LPDEC_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return s->pending.count(ticket) ? LPDEC_EBUSY : LPDEC_ENOTFOUND;
+    if (xhat) std::memcpy(xhat, it->second.xhat.data(), it->second.xhat.size());
+    if (flag) *flag = it->second.flag;
+    if (objective) *objective = it->second.obj;
+    if (latency_s) *latency_s = it->second.latency;
+    s->results.erase(it);
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_server_drain(lpdec_server *s)
+{
+    if (!s) return LPDEC_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->pending.empty(); });
+    return LPDEC_OK;
+}
+
+extern "C" lpdec_status lpdec_server_destroy(lpdec_server *s)
+{
+    if (!s) return LPDEC_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &L : s->lanes) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        ws_free(L.ws);
+        ws_free(L.io);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+    }
+    delete s;
+    return LPDEC_OK;
+}

@@ -1,0 +1,153 @@
+// Shared host/device definitions of the decoder: options, code view, per-frame memory plan.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lpdec.h"
+
+namespace lpdec {
+
+// Options as the kernels see them.
+struct Opts {
+    int malp_mode;   // 0: MALP-A, 1: MALP-B
+    int malp_max;
+    int ipm_max;
+    int pcg_maxit;
+    int ref_max;
+    int precond;     // 1: triangular preconditioner, 0: M = I
+    double tau_viol, tau_act, tau_int;
+    double eps, sigma, eta;
+    double pcg_tol, ref_tol, xi_tol;
+};
+
+// Device view of one parity-check matrix H (rows = checks, columns = variables).
+struct CodeView {
+    int m, n, E;
+    const int *rowptr;   // [m+1] CSR
+    const int *col;      // [E]   variable of each CSR edge (ascending within a row)
+    const int *colptr;   // [n+1] CSC
+    const int *vlist;    // [E]   CSC entries: (check << 5) | position of the variable in the check's row
+};
+
+// Byte offsets of every per-frame array. "hot" arrays are touched in every PCG iteration
+// or by the triangular-set search and live in LDS when they fit; "cold" arrays hold the
+// FP64 interior-point state and always live in the frame's global workspace.
+struct Plan {
+    // hot, PT = PCG element type
+    size_t h, r, zz, l, yv, idm, om, t, d2f;   // PT
+    size_t vmask;                              // u32 [m]
+    size_t sg;                                 // i8  [n]   channel sign of each variable
+    size_t pair, pairrow, rnd, lb, lf;         // i32
+    size_t blist, flist, boff, foff;           // i32
+    size_t killkey;                            // u64 [m]
+    size_t status;                             // i32 [n]   residual degree (Algorithm 7)
+    size_t hot_bytes;
+    // cold, FP64 unless noted
+    size_t x, z, dx, dz, rc, tq, d2;           // [n+m]
+    size_t y, dy, rb, w, b, rho, f64;          // [m]
+    size_t c64;                                // 8 x [m] FP64 PCG vectors (escalation), dy copy
+    size_t u, g;                               // [n]
+    size_t active;                             // u8 [m]
+    size_t cold_bytes;
+};
+
+__host__ __device__ inline size_t lp_align(size_t v) { return (v + 15) & ~(size_t)15; }
+
+__host__ __device__ inline Plan make_plan(int m, int n, int pt_size)
+{
+    Plan p;
+    size_t o = 0;
+    const size_t M = (size_t)m, N = (size_t)n, Q = (size_t)n + m, P = (size_t)pt_size;
+    p.h = o; o = lp_align(o + P * M);
+    p.r = o; o = lp_align(o + P * M);
+    p.zz = o; o = lp_align(o + P * M);
+    p.l = o; o = lp_align(o + P * M);
+    p.yv = o; o = lp_align(o + P * M);
+    p.idm = o; o = lp_align(o + P * M);
+    p.om = o; o = lp_align(o + P * M);
+    p.t = o; o = lp_align(o + P * Q);
+    p.d2f = o; o = lp_align(o + P * Q);
+    p.killkey = o; o = lp_align(o + 8 * M);
+    p.vmask = o; o = lp_align(o + 4 * M);
+    p.pair = o; o = lp_align(o + 4 * M);
+    p.pairrow = o; o = lp_align(o + 4 * N);
+    p.rnd = o; o = lp_align(o + 4 * M);
+    p.lb = o; o = lp_align(o + 4 * M);
+    p.lf = o; o = lp_align(o + 4 * M);
+    p.blist = o; o = lp_align(o + 4 * M);
+    p.flist = o; o = lp_align(o + 4 * M);
+    p.boff = o; o = lp_align(o + 4 * (M + 1));
+    p.foff = o; o = lp_align(o + 4 * (M + 1));
+    p.sg = o; o = lp_align(o + N);
+    p.status = o; o = lp_align(o + 4 * N);
+    p.hot_bytes = o;
+    o = 0;
+    p.x = o; o = lp_align(o + 8 * Q);
+    p.z = o; o = lp_align(o + 8 * Q);
+    p.dx = o; o = lp_align(o + 8 * Q);
+    p.dz = o; o = lp_align(o + 8 * Q);
+    p.rc = o; o = lp_align(o + 8 * Q);
+    p.tq = o; o = lp_align(o + 8 * Q);
+    p.d2 = o; o = lp_align(o + 8 * Q);
+    p.y = o; o = lp_align(o + 8 * M);
+    p.dy = o; o = lp_align(o + 8 * M);
+    p.rb = o; o = lp_align(o + 8 * M);
+    p.w = o; o = lp_align(o + 8 * M);
+    p.b = o; o = lp_align(o + 8 * M);
+    p.rho = o; o = lp_align(o + 8 * M);
+    p.f64 = o; o = lp_align(o + 8 * M);
+    p.c64 = o; o = o + 8 * lp_align(8 * M);
+    p.u = o; o = lp_align(o + 8 * N);
+    p.g = o; o = lp_align(o + 8 * N);
+    p.active = o; o = lp_align(o + M);
+    p.cold_bytes = o;
+    return p;
+}
+
+// What a launch asks the decode kernel to do.
+enum Mode : int {
+    MODE_DECODE = 0,      // full MALP decode
+    MODE_IPM = 1,         // one LP (cut set given) -> x, y, z
+    MODE_SOLVE = 2,       // one Newton solve on given d2, w
+    MODE_MATVEC = 3,      // l = A D^2 A^T h
+    MODE_MTS = 4,         // Algorithm 7 + levels
+    MODE_CUTS = 5,        // Algorithm 2 on every check
+};
+
+// Kernel arguments (one struct, passed by value).
+struct Args {
+    CodeView code;
+    Opts o;
+    Plan plan;
+    int nframes;
+    int mode;
+    int hot_in_lds;
+    char *hot_ws;          // per-frame hot arena in global memory when not in LDS
+    char *cold_ws;         // per-frame cold arena
+    size_t hot_stride, cold_stride;
+    // inputs
+    const void *gamma;     // [nframes*n] float or double
+    int gamma_f64;
+    const uint32_t *vmask_in;  // [nframes*m]   (IPM, SOLVE, MATVEC)
+    const uint8_t *hascut_in;  // [nframes*m]   (MTS)
+    const float *w_in;         // [nframes*(n+m)] (MTS)
+    const double *d2_in;       // [nframes*(n+m)] (SOLVE, MATVEC)
+    const double *vec_in;      // [nframes*m] h (MATVEC) or w (SOLVE); [nframes*n] u (CUTS)
+    // outputs
+    uint8_t *xhat;             // [nframes*n]
+    int32_t *flag;             // [nframes]
+    double *obj;               // [nframes]
+    lpdec_stats *stats;        // [nframes]
+    double *u_out;             // [nframes*n]
+    uint32_t *trace;           // [nframes*trace_cap*m]
+    int trace_cap;
+    double *vec_out;           // y (SOLVE) [nframes*m], l (MATVEC) [nframes*m], lhs (CUTS)
+    double *x_out, *z_out;     // [nframes*(n+m)] (IPM)
+    int32_t *i_out;            // iterations / pair / rounds
+    int32_t *i_out2, *i_out3;  // status / lev_b / lev_f
+    double *d_out;             // residual (SOLVE)
+    uint32_t *u32_out;         // vmask (CUTS)
+    uint8_t *u8_out;           // viol (CUTS)
+};
+
+}  // namespace lpdec

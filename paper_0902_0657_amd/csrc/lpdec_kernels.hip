@@ -1,0 +1,185 @@
+// Kernel entry points: one workgroup per frame. The per-frame "hot" arena (PCG vectors,
+// triangular-set search state, level lists) sits in LDS when it fits and in the frame's
+// global workspace otherwise; HOT_LDS selects the placement at compile time so that the
+// compiler emits LDS instructions for the LDS instantiation.
+#include <hip/hip_runtime.h>
+
+#include "lpdec_device.hpp"
+#include "lpdec_launch.hpp"
+
+namespace lpdec {
+
+template <typename PT>
+LPD_INLINE void run_ipm(Frame<PT> &F, const Args &a, int f)
+{
+    const int m = F.m, n = F.n;
+    F.load_gamma(a, f);
+    for (int j = F.tid; j < m; j += F.nt) F.vmask[j] = a.vmask_in[(size_t)f * m + j];
+    int pl = 0;
+    for (int j = F.tid; j < m; j += F.nt) pl += a.vmask_in[(size_t)f * m + j] != 0u;
+    F.p = block_sum1(pl, F.sc);
+    lpdec_stats st = {};
+    int its = 0;
+    const int status = F.ipm(st, its);
+    const size_t q = (size_t)n + m;
+    for (int c = F.tid; c < n + m; c += F.nt) {
+        const bool pr = F.colpresent(c);
+        a.x_out[f * q + c] = pr ? F.x[c] : 0.0;
+        a.z_out[f * q + c] = pr ? F.z[c] : 0.0;
+    }
+    for (int j = F.tid; j < m; j += F.nt) a.vec_out[(size_t)f * m + j] = F.cut(j) ? F.y[j] : 0.0;
+    if (F.tid == 0) {
+        a.i_out[f] = its;
+        a.i_out2[f] = status;
+        if (a.stats) { st.status = status; st.ipm_iters = its; a.stats[f] = st; }
+    }
+}
+
+template <typename PT>
+LPD_INLINE void run_solve(Frame<PT> &F, const Args &a, int f)
+{
+    const int m = F.m, n = F.n;
+    const size_t q = (size_t)n + m;
+    F.load_gamma(a, f);
+    for (int j = F.tid; j < m; j += F.nt) {
+        F.vmask[j] = a.vmask_in[(size_t)f * m + j];
+        F.w[j] = a.vec_in[(size_t)f * m + j];
+    }
+    for (int c = F.tid; c < n + m; c += F.nt) {
+        const double dd = a.d2_in[f * q + c];
+        F.d2[c] = dd;
+        F.set_d2f(c, dd);
+    }
+    int pl = 0;
+    for (int j = F.tid; j < m; j += F.nt) pl += a.vmask_in[(size_t)f * m + j] != 0u;
+    F.p = block_sum1(pl, F.sc);
+    if (F.o.precond) F.mts(nullptr);
+    else F.slack_basis();
+    F.build_levels();
+    int refr = 0, escal = 0;
+    double resid2 = 0.0;
+    const int its = F.solve(0.0, refr, escal, resid2);
+    for (int j = F.tid; j < m; j += F.nt) a.vec_out[(size_t)f * m + j] = F.cut(j) ? F.dy[j] : 0.0;
+    if (F.tid == 0) {
+        if (a.i_out) a.i_out[f] = its;
+        if (a.d_out) a.d_out[f] = sqrt(resid2);
+    }
+}
+
+template <typename PT>
+LPD_INLINE void run_matvec(Frame<PT> &F, const Args &a, int f)
+{
+    const int m = F.m, n = F.n;
+    const size_t q = (size_t)n + m;
+    F.load_gamma(a, f);
+    for (int j = F.tid; j < m; j += F.nt) {
+        F.vmask[j] = a.vmask_in[(size_t)f * m + j];
+        F.h[j] = (PT)a.vec_in[(size_t)f * m + j];
+    }
+    for (int c = F.tid; c < n + m; c += F.nt) F.d2f[c] = (PT)a.d2_in[f * q + c];
+    __syncthreads();
+    for (int i = F.tid; i < n; i += F.nt) F.t[i] = F.d2f[i] * F.template col_dot<PT>(i, F.h);
+    __syncthreads();
+    for (int j = F.tid; j < m; j += F.nt) {
+        double out = 0.0;
+        if (F.cut(j)) {
+            const int e0 = F.cd.rowptr[j], e1 = F.cd.rowptr[j + 1];
+            PT s = F.d2f[n + j] * F.h[j];
+            for (int e = e0; e < e1; ++e) {
+                const int i = F.cd.col[e];
+                s += F.aent(j, e - e0, i) > 0 ? F.t[i] : -F.t[i];
+            }
+            out = (double)s;
+        }
+        a.vec_out[(size_t)f * m + j] = out;
+    }
+}
+
+template <typename PT>
+LPD_INLINE void run_mts(Frame<PT> &F, const Args &a, int f)
+{
+    const int m = F.m, n = F.n;
+    for (int j = F.tid; j < m; j += F.nt) F.vmask[j] = a.hascut_in[(size_t)f * m + j] ? 1u : 0u;
+    __syncthreads();
+    const int rounds = F.mts(a.w_in + (size_t)f * (n + m));
+    for (int j = F.tid; j < m; j += F.nt) {
+        a.i_out[(size_t)f * m + j] = F.pair[j];
+        a.i_out2[(size_t)f * m + j] = F.lb[j];
+        a.i_out3[(size_t)f * m + j] = F.lf[j];
+    }
+    if (F.tid == 0 && a.flag) a.flag[f] = rounds;
+}
+
+template <typename PT>
+LPD_INLINE void run_cuts(Frame<PT> &F, const Args &a, int f)
+{
+    const int m = F.m, n = F.n;
+    for (int i = F.tid; i < n; i += F.nt) F.u[i] = a.vec_in[(size_t)f * n + i];
+    __syncthreads();
+    for (int j = F.tid; j < m; j += F.nt) {
+        uint32_t V;
+        double lhs;
+        const int v = F.find_cut(j, V, lhs);
+        a.u32_out[(size_t)f * m + j] = V;
+        a.u8_out[(size_t)f * m + j] = (uint8_t)v;
+        if (a.vec_out) a.vec_out[(size_t)f * m + j] = lhs;
+    }
+}
+
+template <typename PT, bool HOT_LDS, int MODE>
+__global__ void __launch_bounds__(1024) lpdec_main(Args a)
+{
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ Scratch sc;
+    const int f = blockIdx.x;
+    if (f >= a.nframes) return;
+    char *hot = HOT_LDS ? lds_dyn : a.hot_ws + (size_t)f * a.hot_stride;
+    char *cold = a.cold_ws + (size_t)f * a.cold_stride;
+    Frame<PT> F;
+    F.bind(a, hot, cold, &sc);
+    if constexpr (MODE == MODE_DECODE) F.decode(a, f);
+    else if constexpr (MODE == MODE_IPM) run_ipm(F, a, f);
+    else if constexpr (MODE == MODE_SOLVE) run_solve(F, a, f);
+    else if constexpr (MODE == MODE_MATVEC) run_matvec(F, a, f);
+    else if constexpr (MODE == MODE_MTS) run_mts(F, a, f);
+    else if constexpr (MODE == MODE_CUTS) run_cuts(F, a, f);
+}
+
+size_t static_lds_bytes() { return sizeof(Scratch); }
+
+template <typename PT, bool HOT_LDS, int MODE>
+static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream_t stream)
+{
+    if (HOT_LDS) {
+        // raises the dynamic-LDS limit of this kernel to what the hot arena needs
+        (void)hipFuncSetAttribute((const void *)lpdec_main<PT, HOT_LDS, MODE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    }
+    hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(a.nframes), dim3(block),
+                       HOT_LDS ? lds_bytes : 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename PT, bool HOT_LDS>
+static hipError_t launch_m(const Args &a, int block, size_t lds_bytes, hipStream_t stream)
+{
+    switch (a.mode) {
+    case MODE_DECODE: return launch_t<PT, HOT_LDS, MODE_DECODE>(a, block, lds_bytes, stream);
+    case MODE_IPM: return launch_t<PT, HOT_LDS, MODE_IPM>(a, block, lds_bytes, stream);
+    case MODE_SOLVE: return launch_t<PT, HOT_LDS, MODE_SOLVE>(a, block, lds_bytes, stream);
+    case MODE_MATVEC: return launch_t<PT, HOT_LDS, MODE_MATVEC>(a, block, lds_bytes, stream);
+    case MODE_MTS: return launch_t<PT, HOT_LDS, MODE_MTS>(a, block, lds_bytes, stream);
+    case MODE_CUTS: return launch_t<PT, HOT_LDS, MODE_CUTS>(a, block, lds_bytes, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream)
+{
+    if (pt64) return a.hot_in_lds ? launch_m<double, true>(a, block, lds_bytes, stream)
+                                  : launch_m<double, false>(a, block, lds_bytes, stream);
+    return a.hot_in_lds ? launch_m<float, true>(a, block, lds_bytes, stream)
+                        : launch_m<float, false>(a, block, lds_bytes, stream);
+}
+
+}  // namespace lpdec

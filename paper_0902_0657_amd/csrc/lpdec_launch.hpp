@@ -1,0 +1,15 @@
+// Host-side launcher of the per-frame decode kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lpdec_common.hpp"
+
+namespace lpdec {
+
+// Launches one workgroup per frame. pt64: PCG in FP64 (1) or FP32 (0). lds_bytes: dynamic
+// LDS for the hot arena when a.hot_in_lds.
+hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream);
+// Static LDS used by the kernel besides the hot arena.
+size_t static_lds_bytes();
+
+}  // namespace lpdec

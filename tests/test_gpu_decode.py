@@ -1,0 +1,161 @@
+"""GPU parity of the whole decoder against the oracle: decoded word and certificate flag
+bit-exact on every frame, LP objective within a relative 1e-6 (floor 1), per-iteration cut
+sets identical. A frame where the two disagree on integrality fails the test."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth.channel import awgn_llr, batch_awgn, batch_bsc, frame_seed
+from synth.codes import from_dense, irregular_code, regular_code
+from tests.gpu_util import cuda, host, make_ctx, obj_close
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.close()
+
+
+def _code(ctx, code):
+    from paper_0902_0657_amd import Code
+    return Code.from_synth(ctx, code)
+
+
+def _compare(orc, code, G, out, oracle_frames=None, opts=None):
+    xh, fl, ob = host(out["xhat"]), host(out["flag"]), host(out["obj"])
+    frames = range(G.shape[0]) if oracle_frames is None else oracle_frames
+    bad = []
+    for f in frames:
+        r = orc.decode(code, G[f], opts)
+        if not (np.array_equal(xh[f], r.xhat) and fl[f] == r.flag and obj_close(ob[f], r.objective)):
+            bad.append((f, int(fl[f]), r.flag, float(ob[f]), r.objective))
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_config1_n96_all_frames(ctx, orc, precision):
+    """Plain configuration: (3,6) n=96, AWGN 2.0 dB, 200 frames."""
+    import torch
+    code = regular_code(96)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 2.0, 200, stream=1)
+    ctx.set_option("PRECISION", precision)
+    try:
+        out = ctx.decode_batch(C, cuda(G, torch.float64))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("PRECISION", -1)
+    _compare(orc, code, G, out)
+
+
+def test_single_frame_plain_form(ctx, orc):
+    """lpdec_decode: one frame per launch, host pointers, FP64."""
+    code = regular_code(96)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 2.0, 12, stream=1)
+    for f in range(G.shape[0]):
+        xh, flag, obj, st, u = ctx.decode(C, G[f])
+        r = orc.decode(code, G[f])
+        assert np.array_equal(xh, r.xhat) and flag == r.flag and obj_close(obj, r.objective)
+        assert st["malp_iters"] == r.malp_iters
+
+
+@pytest.mark.parametrize("n,snrs", [(96, [1.0, 1.5, 2.5]), (256, [1.5, 2.0])])
+def test_fp32_batches(ctx, orc, n, snrs):
+    import torch
+    code = regular_code(n)
+    C = _code(ctx, code)
+    G = np.concatenate([batch_awgn(code.n, 0.5, s, 40, stream=2, snr_index=i) for i, s in enumerate(snrs)])
+    G = G.astype(np.float32)
+    out = ctx.decode_batch(C, cuda(G, torch.float32))
+    torch.cuda.synchronize()
+    _compare(orc, code, G.astype(np.float64), out)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cut_traces_match(ctx, orc, mode):
+    import torch
+    code = regular_code(96)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 1.5, 24, stream=3)
+    ctx.set_option("MALP_MODE", mode)
+    try:
+        out = ctx.decode_batch_trace(C, cuda(G, torch.float64), trace_cap=60)
+    finally:
+        ctx.set_option("MALP_MODE", 0)
+    tr, st = host(out["trace"]).view(np.uint32), host(out["stats"])
+    opts = orc.OracleOpts(malp_mode=mode)
+    for f in range(G.shape[0]):
+        r = orc.decode(code, G[f], opts, trace=True)
+        assert st[f, 0] == r.malp_iters
+        k = min(r.malp_iters, 60)
+        assert np.array_equal(tr[f, :k], r.trace_mask[:k]), f
+    _compare(orc, code, G, out, opts=opts)
+
+
+def test_irregular_bsc(ctx, orc):
+    import torch
+    code = irregular_code(256)
+    C = _code(ctx, code)
+    G = batch_bsc(code.n, 0.06, 48, stream=4)
+    out = ctx.decode_batch(C, cuda(G, torch.float64))
+    torch.cuda.synchronize()
+    _compare(orc, code, G, out)
+
+
+def test_hamming_pseudocodeword(ctx, orc):
+    """The (7,4,3) pseudocodeword of the remark after Corollary 5."""
+    import torch
+    g = json.load(open(os.path.join(GOLDEN, "hamming743.json")))
+    code = from_dense(np.array(g["H"]))
+    C = _code(ctx, code)
+    G = np.array([g["gamma"]])
+    out = ctx.decode_batch(C, cuda(G, torch.float64), want_u=True)
+    torch.cuda.synchronize()
+    assert host(out["flag"])[0] == 0
+    assert np.abs(host(out["u"])[0] - np.array(g["pseudocodeword"])).max() < 1e-6
+
+
+def test_edge_cases(ctx, orc):
+    """A codeword as hard decision solves no LP; NaN in one frame fails only that frame;
+    an empty batch is a no-op."""
+    import torch
+    code = regular_code(96)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 2.0, 6, stream=5)
+    G[0] = np.abs(G[0]) + 0.1            # hard decision = all-zero codeword
+    G[3, 5] = np.nan
+    out = ctx.decode_batch(C, cuda(G, torch.float64))
+    torch.cuda.synchronize()
+    fl, st, xh = host(out["flag"]), host(out["stats"]), host(out["xhat"])
+    assert fl[0] == 1 and st[0, 0] == 0 and not xh[0].any()
+    assert fl[3] < 0
+    for f in (1, 2, 4, 5):
+        r = orc.decode(code, G[f])
+        assert fl[f] == r.flag and np.array_equal(xh[f], r.xhat)
+    empty = ctx.decode_batch(C, cuda(np.zeros((0, code.n)), torch.float64))
+    torch.cuda.synchronize()
+    assert empty["flag"].numel() == 0
+
+
+def test_config2_n1024_sampled(ctx, orc):
+    """(3,6) n=1024, 512 frames per launch in FP32-PCG mode (the benchmark's launch); the
+    oracle checks a sample of frames at each Eb/N0, every frame checks p <= m."""
+    import torch
+    code = regular_code(1024)
+    C = _code(ctx, code)
+    snrs = [1.5, 2.0, 2.5]
+    G = np.concatenate([batch_awgn(code.n, 0.5, s, 171 if i < 2 else 170, stream=6, snr_index=i)
+                        for i, s in enumerate(snrs)]).astype(np.float32)
+    out = ctx.decode_batch(C, cuda(G, torch.float32))
+    torch.cuda.synchronize()
+    st, fl = host(out["stats"]), host(out["flag"])
+    assert np.all(st[:, 3] <= code.m) and np.all(fl >= 0)
+    sample = [0, 1, 2, 171, 172, 173, 342, 343, 344]
+    _compare(orc, code, G.astype(np.float64), out, oracle_frames=sample)
