@@ -16,8 +16,8 @@
  *     failure of a context. A numerical failure of one frame is NOT an API error: it is
  *     reported in that frame's flag (< 0).
  *   - H is given in CSR form: rows = checks (m), columns = variables (n), 0-based, column
- *     indices strictly increasing within a row, no empty row, row degree <= 32. The library
- *     copies H; the caller keeps ownership of its arrays.
+ *     indices strictly increasing within a row, no empty row, row degree <= 32,
+ *     m + n <= 16383. The library copies H; the caller keeps ownership of its arrays.
  *   - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory of the
  *     context's device (for example torch CUDA tensors), owned by the caller.
  *   - Batched layouts are frame-major: element i of frame f of an n-vector is at f*n + i.
@@ -101,7 +101,7 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   REF_MAX        refinement rounds after the first solve (3)
  *   IPM_MAX        IPM iteration cap per LP (100)
  *   MALP_MAX       MALP iteration cap (200)
- *   BLOCK          threads per frame (64..1024, multiple of 64; 0 = automatic)
+ *   BLOCK          threads per frame (64..256, multiple of 64; 0 = automatic)
  *   PRECOND        1 = triangular preconditioner (Algorithm 7), 0 = the slack columns as
  *                  preconditioning set (a diagonal preconditioner)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual

@@ -115,20 +115,20 @@ void default_opts(lpdec::Opts &o)
 lpdec::CodeView view(const lpdec_code *c)
 {
     lpdec::CodeView v;
-    v.m = c->m; v.n = c->n; v.E = c->E;
+    v.m = c->m; v.n = c->n; v.E = c->E; v.dcmax = c->dcmax; v.dvmax = c->dvmax;
     v.rowptr = c->d_rowptr; v.col = c->d_col; v.colptr = c->d_colptr; v.vlist = c->d_vlist;
     return v;
 }
 
 int auto_block(const lpdec_code *c)
 {
-    // enough lanes that one pass over the columns needs few iterations, without making the
-    // per-level barriers of the triangular solves wider than the work in a level
+    // the triangular solves and Algorithm 7 run level by level / step by step with little
+    // work per step, so one wave per frame for codes up to a few thousand columns; wider
+    // blocks only for long codes, whose column passes dominate
     const int q = c->n + c->m;
-    if (q <= 800) return 128;
-    if (q <= 3200) return 256;
-    if (q <= 8000) return 512;
-    return 1024;
+    if (q <= 3200) return 64;
+    if (q <= 8000) return 128;
+    return 256;
 }
 
 // Fills the launch geometry and workspace of Args; launches one workgroup per frame.
@@ -138,7 +138,7 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     if (a.nframes <= 0) return LPDEC_OK;
     a.code = view(code);
     a.o = ctx->opts;
-    a.plan = lpdec::make_plan(code->m, code->n, pt64 ? 8 : 4);
+    a.plan = lpdec::make_plan(code->m, code->n, code->dcmax, code->dvmax, pt64 ? 8 : 4);
     const size_t lds_need = a.plan.hot_bytes;
     const size_t lds_avail = (size_t)ctx->lds_limit - lpdec::static_lds_bytes() - 256;
     a.hot_in_lds = lds_need <= lds_avail;
@@ -222,7 +222,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_IPM_MAX: if (!ipos(1)) break; o.ipm_max = (int)v; return LPDEC_OK;
     case LPDEC_OPT_MALP_MAX: if (!ipos(1)) break; o.malp_max = (int)v; return LPDEC_OK;
     case LPDEC_OPT_BLOCK:
-        if (!(v == 0 || (ipos(64) && v <= 1024 && ((int)v % 64) == 0))) break;
+        if (!(v == 0 || (ipos(64) && v <= 256 && ((int)v % 64) == 0))) break;
         ctx->block = (int)v;
         return LPDEC_OK;
     case LPDEC_OPT_PRECOND: if (v != 0 && v != 1) break; o.precond = (int)v; return LPDEC_OK;
@@ -266,7 +266,8 @@ extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, 
     if (!ctx) return LPDEC_EINVAL;
     if (!out || !rowptr || !col) return fail(ctx, LPDEC_EINVAL, "null argument");
     *out = nullptr;
-    if (m <= 0 || n <= 0 || m >= (1 << 26)) return fail(ctx, LPDEC_EINVAL, "bad sizes m=%d n=%d", m, n);
+    if (m <= 0 || n <= 0 || m + n > 16383)
+        return fail(ctx, LPDEC_EINVAL, "bad sizes m=%d n=%d (need m, n > 0 and m + n <= 16383)", m, n);
     if (rowptr[0] != 0) return fail(ctx, LPDEC_EINVAL, "rowptr[0] != 0");
     int dcmax = 0;
     for (int j = 0; j < m; ++j) {
@@ -545,7 +546,7 @@ namespace {
 
 size_t frame_footprint(const lpdec_code *c, int pt64)
 {
-    Plan p = lpdec::make_plan(c->m, c->n, pt64 ? 8 : 4);
+    Plan p = lpdec::make_plan(c->m, c->n, c->dcmax, c->dvmax, pt64 ? 8 : 4);
     // cold arena + hot arena (counted even when it lives in LDS) + gamma + outputs
     return p.cold_bytes + p.hot_bytes + 8 * (size_t)c->n + (size_t)c->n + 64;
 }

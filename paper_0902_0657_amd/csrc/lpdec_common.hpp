@@ -23,29 +23,32 @@ struct Opts {
 // Device view of one parity-check matrix H (rows = checks, columns = variables).
 struct CodeView {
     int m, n, E;
+    int dcmax, dvmax;    // largest check / variable degree
     const int *rowptr;   // [m+1] CSR
     const int *col;      // [E]   variable of each CSR edge (ascending within a row)
     const int *colptr;   // [n+1] CSC
     const int *vlist;    // [E]   CSC entries: (check << 5) | position of the variable in the check's row
 };
 
-// Byte offsets of every per-frame array. "hot" arrays are touched in every PCG iteration
-// or by the triangular-set search and live in LDS when they fit; "cold" arrays hold the
-// FP64 interior-point state and always live in the frame's global workspace.
+// Byte offsets of every per-frame array. "hot" arrays are touched by every PCG iteration or
+// by the triangular-set search; they live in LDS when they fit (else in the frame's global
+// workspace). "cold" arrays hold the FP64 interior-point state in the global workspace.
+// Index lists are uint16 (bit 15 = negative coefficient, bit 14 = row reference, bits
+// 0..13 = index), which bounds n + m by 16383.
 struct Plan {
-    // hot, PT = PCG element type
-    size_t h, r, zz, l, yv, idm, om, t, d2f;   // PT
+    // hot
+    size_t h, r, v, l, s, idm, om, t, d2f;     // PT: [m] x 7, [n+m] x 2
+    size_t rlist, clist, bins, fins;           // u16 [m*dc], [n*dv], [m*(dc+1)], [m*dv]
+    size_t pair, pairrow, lbv, lfv, order;     // i16 [m], [n], [m], [m], [m]
+    size_t boff, foff;                         // i32 [m+1]
+    size_t deg, sg;                            // u8 / i8 [n]
     size_t vmask;                              // u32 [m]
-    size_t sg;                                 // i8  [n]   channel sign of each variable
-    size_t pair, pairrow, rnd, lb, lf;         // i32
-    size_t blist, flist, boff, foff;           // i32
-    size_t killkey;                            // u64 [m]
-    size_t status;                             // i32 [n]   residual degree (Algorithm 7)
+    size_t lbest, ldirty;                      // u64 [64], u32 [64]
     size_t hot_bytes;
     // cold, FP64 unless noted
     size_t x, z, dx, dz, rc, tq, d2;           // [n+m]
     size_t y, dy, rb, w, b, rho, f64;          // [m]
-    size_t c64;                                // 8 x [m] FP64 PCG vectors (escalation), dy copy
+    size_t c64;                                // 8 x [m]: FP64 PCG vectors (escalation), dy copy
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
     size_t cold_bytes;
@@ -53,33 +56,37 @@ struct Plan {
 
 __host__ __device__ inline size_t lp_align(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline Plan make_plan(int m, int n, int pt_size)
+__host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_size)
 {
     Plan p;
     size_t o = 0;
     const size_t M = (size_t)m, N = (size_t)n, Q = (size_t)n + m, P = (size_t)pt_size;
+    const size_t DC = (size_t)dc, DV = (size_t)dv;
     p.h = o; o = lp_align(o + P * M);
     p.r = o; o = lp_align(o + P * M);
-    p.zz = o; o = lp_align(o + P * M);
+    p.v = o; o = lp_align(o + P * M);
     p.l = o; o = lp_align(o + P * M);
-    p.yv = o; o = lp_align(o + P * M);
+    p.s = o; o = lp_align(o + P * M);
     p.idm = o; o = lp_align(o + P * M);
     p.om = o; o = lp_align(o + P * M);
     p.t = o; o = lp_align(o + P * Q);
     p.d2f = o; o = lp_align(o + P * Q);
-    p.killkey = o; o = lp_align(o + 8 * M);
+    p.lbest = o; o = lp_align(o + 8 * 64);
     p.vmask = o; o = lp_align(o + 4 * M);
-    p.pair = o; o = lp_align(o + 4 * M);
-    p.pairrow = o; o = lp_align(o + 4 * N);
-    p.rnd = o; o = lp_align(o + 4 * M);
-    p.lb = o; o = lp_align(o + 4 * M);
-    p.lf = o; o = lp_align(o + 4 * M);
-    p.blist = o; o = lp_align(o + 4 * M);
-    p.flist = o; o = lp_align(o + 4 * M);
     p.boff = o; o = lp_align(o + 4 * (M + 1));
     p.foff = o; o = lp_align(o + 4 * (M + 1));
+    p.ldirty = o; o = lp_align(o + 4 * 64);
+    p.rlist = o; o = lp_align(o + 2 * M * DC);
+    p.clist = o; o = lp_align(o + 2 * N * DV);
+    p.bins = o; o = lp_align(o + 2 * M * (DC + 1));
+    p.fins = o; o = lp_align(o + 2 * M * DV);
+    p.pair = o; o = lp_align(o + 2 * M);
+    p.pairrow = o; o = lp_align(o + 2 * N);
+    p.lbv = o; o = lp_align(o + 2 * M);
+    p.lfv = o; o = lp_align(o + 2 * M);
+    p.order = o; o = lp_align(o + 2 * M);
+    p.deg = o; o = lp_align(o + N);
     p.sg = o; o = lp_align(o + N);
-    p.status = o; o = lp_align(o + 4 * N);
     p.hot_bytes = o;
     o = 0;
     p.x = o; o = lp_align(o + 8 * Q);

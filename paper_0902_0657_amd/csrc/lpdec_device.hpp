@@ -11,6 +11,11 @@
 //     n+j of the row of check j (present only when check j has a cut).
 //   A entry of (row j, standard column i at position k of row j):
 //     sg[i] * (+1 if bit k of vmask[j] is set, else -1); the slack entry is +1.
+//
+// Everything a PCG iteration or a step of Algorithm 7 reads sits in LDS: per LP the row and
+// column lists of A with the signs folded in (rlist, clist), per interior-point iteration the
+// instruction lists of the two triangular solves in level order (bins, fins). Global memory
+// holds the FP64 interior-point state, touched a few times per interior-point iteration.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -22,19 +27,93 @@ namespace lpdec {
 
 #define LPD_INLINE __device__ __forceinline__
 
-constexpr int kMaxWaves = 16;   // up to 1024 threads per frame
+constexpr int kMaxWaves = 4;    // up to 256 threads per frame
+constexpr uint16_t kEnd = 0xFFFF;
 
-// -------------------------------------------------------------------- block primitives
-template <typename T>
-LPD_INLINE T wave_sum(T v)
+// -------------------------------------------------------------------- list entries
+// bit 15: the coefficient is -1; bit 14: the entry refers to a row value; bits 0..13: index.
+LPD_INLINE uint16_t enc(int idx, bool neg, bool rowref = false)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return (uint16_t)((neg ? 0x8000u : 0u) | (rowref ? 0x4000u : 0u) | (unsigned)idx);
+}
+LPD_INLINE int e_idx(uint16_t e) { return e & 0x3FFF; }
+LPD_INLINE bool e_neg(uint16_t e) { return (e & 0x8000u) != 0; }
+LPD_INLINE bool e_row(uint16_t e) { return (e & 0x4000u) != 0; }
+template <typename T>
+LPD_INLINE T sgnv(uint16_t e, T v) { return e_neg(e) ? -v : v; }
+
+// -------------------------------------------------------------------- wave reductions
+// Inclusive scan inside rows of 16 lanes (row_shr 1, 2, 4, 8), then across rows
+// (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2 and 3); lane 63 ends up with the
+// reduction of the wave, which readlane hands to every lane. All 64 lanes must be active.
+template <int CTRL, int ROWM>
+LPD_INLINE uint32_t dpp(uint32_t identity, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWM, 0xF, false);
+}
+
+#define LPD_DPP_SCAN(OP, ID, V)           \
+    V = OP(V, dpp<0x111, 0xF>(ID, V));    \
+    V = OP(V, dpp<0x112, 0xF>(ID, V));    \
+    V = OP(V, dpp<0x114, 0xF>(ID, V));    \
+    V = OP(V, dpp<0x118, 0xF>(ID, V));    \
+    V = OP(V, dpp<0x142, 0xA>(ID, V));    \
+    V = OP(V, dpp<0x143, 0xC>(ID, V));
+
+LPD_INLINE uint32_t op_max_u(uint32_t a, uint32_t b) { return a > b ? a : b; }
+LPD_INLINE uint32_t op_add_u(uint32_t a, uint32_t b) { return a + b; }
+LPD_INLINE uint32_t op_add_f(uint32_t a, uint32_t b) { return __float_as_uint(__uint_as_float(a) + __uint_as_float(b)); }
+
+LPD_INLINE uint32_t wave_max_u32(uint32_t v)
+{
+    LPD_DPP_SCAN(op_max_u, 0u, v)
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// max of 64-bit keys: high words first, then the low words of the lanes holding that high word
+LPD_INLINE unsigned long long wave_max_u64(unsigned long long k)
+{
+    const uint32_t hi = wave_max_u32((uint32_t)(k >> 32));
+    const uint32_t lo = wave_max_u32((uint32_t)(k >> 32) == hi ? (uint32_t)k : 0u);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+LPD_INLINE float wave_sum(float v)
+{
+    uint32_t q = __float_as_uint(v);
+    LPD_DPP_SCAN(op_add_f, 0u, q)
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)q, 63));
+}
+
+LPD_INLINE int wave_sum(int v)
+{
+    uint32_t q = (uint32_t)v;
+    LPD_DPP_SCAN(op_add_u, 0u, q)
+    return __builtin_amdgcn_readlane((int)q, 63);
+}
+
+LPD_INLINE double wave_sum(double v)
+{
+#define LPD_DSTEP(CTRL, ROWM)                                                   \
+    {                                                                         \
+        const uint32_t lo = dpp<CTRL, ROWM>(0u, (uint32_t)__double2loint(v)); \
+        const uint32_t hi = dpp<CTRL, ROWM>(0u, (uint32_t)__double2hiint(v)); \
+        v = v + __hiloint2double((int)hi, (int)lo);                           \
+    }
+    LPD_DSTEP(0x111, 0xF)
+    LPD_DSTEP(0x112, 0xF)
+    LPD_DSTEP(0x114, 0xF)
+    LPD_DSTEP(0x118, 0xF)
+    LPD_DSTEP(0x142, 0xA)
+    LPD_DSTEP(0x143, 0xC)
+#undef LPD_DSTEP
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 template <typename T>
-LPD_INLINE T wave_max(T v)
+LPD_INLINE T wave_max_t(T v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -45,7 +124,7 @@ LPD_INLINE T wave_max(T v)
 }
 
 template <typename T>
-LPD_INLINE T wave_min(T v)
+LPD_INLINE T wave_min_t(T v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -55,6 +134,7 @@ LPD_INLINE T wave_min(T v)
     return v;
 }
 
+// -------------------------------------------------------------------- block reductions
 // Shared scratch for reductions: kMaxWaves slots per value, up to 4 values.
 struct Scratch {
     double d[4 * kMaxWaves];
@@ -67,10 +147,11 @@ template <int K, typename T>
 LPD_INLINE void block_sum(T (&v)[K], Scratch *s)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    T *buf = reinterpret_cast<T *>(s->d);
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
     __syncthreads();
+    if (nw == 1) return;
+    T *buf = reinterpret_cast<T *>(s->d);
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) buf[k * kMaxWaves + wv] = v[k];
@@ -81,6 +162,7 @@ LPD_INLINE void block_sum(T (&v)[K], Scratch *s)
         for (int w = 0; w < nw; ++w) a += buf[k * kMaxWaves + w];
         v[k] = a;
     }
+    __syncthreads();
 }
 
 template <typename T>
@@ -91,44 +173,49 @@ LPD_INLINE T block_sum1(T v, Scratch *s)
     return a[0];
 }
 
-// [0] summed, [1] maximised over the block.
+// [0] summed, [1] maximised (values >= 0) over the block.
 template <typename T>
 LPD_INLINE void block_summax(T (&v)[2], Scratch *s)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    T *buf = reinterpret_cast<T *>(s->d);
     v[0] = wave_sum(v[0]);
-    v[1] = wave_max(v[1]);
+    v[1] = wave_max_t(v[1]);
     __syncthreads();
+    if (nw == 1) return;
+    T *buf = reinterpret_cast<T *>(s->d);
     if (lane == 0) { buf[wv] = v[0]; buf[kMaxWaves + wv] = v[1]; }
     __syncthreads();
-    T a = 0, b = buf[kMaxWaves];
+    T a = 0, b = 0;
     for (int w = 0; w < nw; ++w) {
         a += buf[w];
         b = buf[kMaxWaves + w] > b ? buf[kMaxWaves + w] : b;
     }
     v[0] = a;
     v[1] = b;
+    __syncthreads();
 }
 
 LPD_INLINE double block_max_d(double v, Scratch *s)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_max(v);
+    v = wave_max_t(v);
     __syncthreads();
+    if (nw == 1) return v;
     if (lane == 0) s->d[wv] = v;
     __syncthreads();
     double a = s->d[0];
     for (int w = 1; w < nw; ++w) a = s->d[w] > a ? s->d[w] : a;
+    __syncthreads();
     return a;
 }
 
 LPD_INLINE void block_min2(double &a, double &b, Scratch *s)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    a = wave_min(a);
-    b = wave_min(b);
+    a = wave_min_t(a);
+    b = wave_min_t(b);
     __syncthreads();
+    if (nw == 1) return;
     if (lane == 0) { s->d[wv] = a; s->d[kMaxWaves + wv] = b; }
     __syncthreads();
     a = s->d[0];
@@ -137,35 +224,42 @@ LPD_INLINE void block_min2(double &a, double &b, Scratch *s)
         a = s->d[w] < a ? s->d[w] : a;
         b = s->d[kMaxWaves + w] < b ? s->d[kMaxWaves + w] : b;
     }
+    __syncthreads();
 }
 
 LPD_INLINE int block_or(int v, Scratch *s)
 {
     const unsigned long long bal = __ballot(v != 0);
+    const int nw = blockDim.x >> 6;
     __syncthreads();
+    if (nw == 1) return bal != 0ull;
     if (threadIdx.x == 0) s->i[0] = 0;
     __syncthreads();
     if ((threadIdx.x & 63) == 0 && bal) atomicOr(&s->i[0], 1);
     __syncthreads();
-    return s->i[0];
+    const int r = s->i[0];
+    __syncthreads();
+    return r;
 }
 
 LPD_INLINE int block_max_i(int v, Scratch *s)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_max(v);
+    v = wave_max_t(v);
     __syncthreads();
+    if (nw == 1) return v;
     if (lane == 0) reinterpret_cast<int *>(s->d)[wv] = v;
     __syncthreads();
     int a = reinterpret_cast<int *>(s->d)[0];
     for (int w = 1; w < nw; ++w) {
-        int b = reinterpret_cast<int *>(s->d)[w];
+        const int b = reinterpret_cast<int *>(s->d)[w];
         a = b > a ? b : a;
     }
+    __syncthreads();
     return a;
 }
 
-// Exclusive scan over cnt[0..len) in place (one wave does it, chunks of 64); the others wait.
+// Exclusive scan over cnt[0..len) in place (wave 0 does it, chunks of 64); the others wait.
 LPD_INLINE void block_exscan(int *cnt, int len)
 {
     __syncthreads();
@@ -173,11 +267,11 @@ LPD_INLINE void block_exscan(int *cnt, int len)
         const int lane = threadIdx.x;
         int carry = 0;
         for (int base = 0; base < len; base += 64) {
-            int v = (base + lane < len) ? cnt[base + lane] : 0;
+            const int v = (base + lane < len) ? cnt[base + lane] : 0;
             int incl = v;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
-                int t = __shfl_up(incl, o, 64);
+                const int t = __shfl_up(incl, o, 64);
                 if (lane >= o) incl += t;
             }
             if (base + lane < len) cnt[base + lane] = carry + incl - v;
@@ -189,7 +283,7 @@ LPD_INLINE void block_exscan(int *cnt, int len)
 }
 
 // Ordering key of Algorithm 7: float weight descending, then column index ascending,
-// packed so that a larger 64-bit integer means "preferred".
+// packed so that a larger 64-bit integer means "preferred"; 0 means "no column".
 LPD_INLINE unsigned long long mts_key(float w, int c)
 {
     return ((unsigned long long)__float_as_uint(w) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)c);
@@ -201,80 +295,115 @@ template <typename PT>
 struct Frame {
     CodeView cd;
     Opts o;
-    int m, n, tid, nt;
+    int m, n, RW, CW, tid, nt;
     Scratch *sc;
     // hot
-    PT *h, *r, *zz, *l, *yv, *t, *d2f, *idm, *om;
-    uint32_t *vmask;
+    PT *h, *r, *v, *l, *s, *idm, *om, *t, *d2f;
+    uint16_t *rlist, *clist, *bins, *fins;
+    int16_t *pair, *pairrow, *lbv, *lfv, *order;
+    int *boff, *foff;
+    uint8_t *deg;
     int8_t *sg;
-    int *pair, *pairrow, *rnd, *lb, *lf, *blist, *flist, *boff, *foff;
-    unsigned long long *killkey;
-    int *status;
+    uint32_t *vmask;
+    unsigned long long *lbest;
+    uint32_t *ldirty;
     // cold
-    double *x, *z, *dx, *dz, *rc, *tq, *d2, *y, *dy, *rb, *w, *b, *rho, *u, *g, *f64;
+    double *x, *z, *dx, *dz, *rc, *tq, *d2, *y, *dy, *rb, *w, *b, *rho, *f64, *u, *g;
     double *c64[8];   // FP64 PCG vectors for escalated solves, and a copy of dy
     uint8_t *active;
-    // level counts of the current preconditioner
+    // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
 
-    LPD_INLINE void bind(const Args &a, char *hot, char *cold, Scratch *s)
+    LPD_INLINE void bind(const Args &a, char *hot, char *cold, Scratch *scr)
     {
-        cd = a.code; o = a.o; m = cd.m; n = cd.n; tid = threadIdx.x; nt = blockDim.x; sc = s;
+        cd = a.code; o = a.o; m = cd.m; n = cd.n; RW = cd.dcmax; CW = cd.dvmax;
+        tid = threadIdx.x; nt = blockDim.x; sc = scr;
         const Plan &P = a.plan;
-        h = (PT *)(hot + P.h); r = (PT *)(hot + P.r); zz = (PT *)(hot + P.zz); l = (PT *)(hot + P.l);
-        yv = (PT *)(hot + P.yv); t = (PT *)(hot + P.t); d2f = (PT *)(hot + P.d2f); idm = (PT *)(hot + P.idm); om = (PT *)(hot + P.om);
-        vmask = (uint32_t *)(hot + P.vmask); sg = (int8_t *)(hot + P.sg);
-        pair = (int *)(hot + P.pair); pairrow = (int *)(hot + P.pairrow); rnd = (int *)(hot + P.rnd);
-        lb = (int *)(hot + P.lb); lf = (int *)(hot + P.lf); blist = (int *)(hot + P.blist);
-        flist = (int *)(hot + P.flist); boff = (int *)(hot + P.boff); foff = (int *)(hot + P.foff);
-        killkey = (unsigned long long *)(hot + P.killkey); status = (int *)(hot + P.status);
+        h = (PT *)(hot + P.h); r = (PT *)(hot + P.r); v = (PT *)(hot + P.v); l = (PT *)(hot + P.l);
+        s = (PT *)(hot + P.s); idm = (PT *)(hot + P.idm); om = (PT *)(hot + P.om);
+        t = (PT *)(hot + P.t); d2f = (PT *)(hot + P.d2f);
+        rlist = (uint16_t *)(hot + P.rlist); clist = (uint16_t *)(hot + P.clist);
+        bins = (uint16_t *)(hot + P.bins); fins = (uint16_t *)(hot + P.fins);
+        pair = (int16_t *)(hot + P.pair); pairrow = (int16_t *)(hot + P.pairrow);
+        lbv = (int16_t *)(hot + P.lbv); lfv = (int16_t *)(hot + P.lfv); order = (int16_t *)(hot + P.order);
+        boff = (int *)(hot + P.boff); foff = (int *)(hot + P.foff);
+        deg = (uint8_t *)(hot + P.deg); sg = (int8_t *)(hot + P.sg); vmask = (uint32_t *)(hot + P.vmask);
+        lbest = (unsigned long long *)(hot + P.lbest); ldirty = (uint32_t *)(hot + P.ldirty);
         x = (double *)(cold + P.x); z = (double *)(cold + P.z); dx = (double *)(cold + P.dx);
         dz = (double *)(cold + P.dz); rc = (double *)(cold + P.rc); tq = (double *)(cold + P.tq);
         d2 = (double *)(cold + P.d2); y = (double *)(cold + P.y); dy = (double *)(cold + P.dy);
         rb = (double *)(cold + P.rb); w = (double *)(cold + P.w); b = (double *)(cold + P.b);
-        rho = (double *)(cold + P.rho); u = (double *)(cold + P.u); g = (double *)(cold + P.g);
-        f64 = (double *)(cold + P.f64);
+        rho = (double *)(cold + P.rho); f64 = (double *)(cold + P.f64);
+        u = (double *)(cold + P.u); g = (double *)(cold + P.g);
         for (int k = 0; k < 8; ++k) c64[k] = (double *)(cold + P.c64 + (size_t)k * lp_align(8 * (size_t)m));
         active = (uint8_t *)(cold + P.active);
     }
 
     LPD_INLINE bool cut(int j) const { return vmask[j] != 0u; }
     LPD_INLINE bool colpresent(int c) const { return c < n || vmask[c - n] != 0u; }
-    // A entry of row j at position k (variable i)
+    // A entry of row j at position k (variable i), from H, V and the channel signs
     LPD_INLINE int aent(int j, int k, int i) const
     {
         return ((vmask[j] >> k) & 1u) ? (int)sg[i] : -(int)sg[i];
     }
     LPD_INLINE double cost(int c) const { return c < n ? fabs(g[c]) : 0.0; }
 
-    // (A v)_j for a column-space vector v (row j has a cut)
-    template <typename T, typename V>
-    LPD_INLINE T row_dot(int j, const V *v) const
+    // Row and column lists of the LP's A with the signs folded in (rebuilt for every LP).
+    LPD_INLINE void build_lists()
     {
-        const int e0 = cd.rowptr[j], e1 = cd.rowptr[j + 1];
-        T s = (T)v[n + j];
-        for (int e = e0; e < e1; ++e) {
-            const int i = cd.col[e];
-            const T vi = (T)v[i];
-            s += aent(j, e - e0, i) > 0 ? vi : -vi;
+        for (int j = tid; j < m; j += nt) {
+            uint16_t *L = rlist + (size_t)j * RW;
+            if (cut(j)) {
+                const int e0 = cd.rowptr[j], d = cd.rowptr[j + 1] - e0;
+                for (int k = 0; k < RW; ++k) {
+                    if (k < d) {
+                        const int i = cd.col[e0 + k];
+                        L[k] = enc(i, aent(j, k, i) < 0);
+                    } else {
+                        L[k] = kEnd;
+                    }
+                }
+            } else {
+                for (int k = 0; k < RW; ++k) L[k] = kEnd;
+            }
         }
-        return s;
+        for (int i = tid; i < n; i += nt) {
+            uint16_t *L = clist + (size_t)i * CW;
+            int c = 0;
+            for (int e = cd.colptr[i]; e < cd.colptr[i + 1]; ++e) {
+                const int vv = cd.vlist[e], j = vv >> 5;
+                if (cut(j)) L[c++] = enc(j, aent(j, vv & 31, i) < 0);
+            }
+            for (; c < CW; ++c) L[c] = kEnd;
+        }
+        __syncthreads();
+    }
+
+    // (A x)_j over the columns of row j, slack included (row j has a cut)
+    template <typename T, typename V>
+    LPD_INLINE T row_dot(int j, const V *xq) const
+    {
+        const uint16_t *L = rlist + (size_t)j * RW;
+        T acc = (T)xq[n + j];
+        for (int k = 0; k < RW; ++k) {
+            const uint16_t e = L[k];
+            if (e == kEnd) break;
+            acc += sgnv(e, (T)xq[e_idx(e)]);
+        }
+        return acc;
     }
     // (A^T y)_i for standard column i, y in check space
     template <typename T, typename V>
     LPD_INLINE T col_dot(int i, const V *yy) const
     {
-        T s = 0;
-        for (int e = cd.colptr[i]; e < cd.colptr[i + 1]; ++e) {
-            const int v = cd.vlist[e];
-            const int j = v >> 5, k = v & 31;
-            const uint32_t vm = vmask[j];
-            if (vm) {
-                const T yj = (T)yy[j];
-                s += (((vm >> k) & 1u) ? (int)sg[i] : -(int)sg[i]) > 0 ? yj : -yj;
-            }
+        const uint16_t *L = clist + (size_t)i * CW;
+        T acc = 0;
+        for (int k = 0; k < CW; ++k) {
+            const uint16_t e = L[k];
+            if (e == kEnd) break;
+            acc += sgnv(e, (T)yy[e_idx(e)]);
         }
-        return s;
+        return acc;
     }
 
     // ------------------------------------------------------------ Algorithm 2
@@ -292,220 +421,135 @@ struct Frame {
             if (k == 0 || a < best) { best = a; ks = k; }
         }
         V = (cnt & 1) ? S : (S ^ (1u << ks));
-        double s = 0.0;
+        double acc = 0.0;
         for (int k = 0; k < d; ++k) {
             const double uk = u[cd.col[e0 + k]];
-            s += ((V >> k) & 1u) ? (1.0 - uk) : uk;
+            acc += ((V >> k) & 1u) ? (1.0 - uk) : uk;
         }
-        lhs = s;
-        return s < 1.0 - o.tau_viol;
+        lhs = acc;
+        return acc < 1.0 - o.tau_viol;
     }
 
     // ------------------------------------------------------------ Algorithm 7 + levels
     LPD_INLINE float wt(const float *wk, int c) const { return wk ? wk[c] : (float)d2f[c]; }
 
-    // Column-wise greedy search for the triangular set (Algorithm 7), run as parallel rounds
-    // that commit exactly the steps of the sequential algorithm with the key order
-    // (weight descending, column index ascending):
-    //   - a live row's candidate is the preferred degree-1 column in it (its slack always is
-    //     one);
-    //   - a column of residual degree rdeg >= 2 turns degree-1 once rdeg-1 of its rows are
-    //     gone, i.e. when the (rdeg-1)-th largest candidate key of its rows is taken, and from
-    //     then on outranks every candidate below its own key;
-    //   - tau = the largest min(that key, own key) over such columns; a candidate whose key is
-    //     >= tau is the sequential algorithm's choice for its row and is committed now (the
-    //     best candidate overall always is, so every round makes progress).
-    // Columns committed in one round never share a live row, so their updates do not race.
-    // Fills pair (column of each row), pairrow (row of each chosen standard column), rnd
-    // (round of each row), lf (forward-substitution level) and lb (back-substitution level).
-    // Returns the number of rounds.
+    // preferred available column among those owned by one lane (c = lane + 64 k)
+    LPD_INLINE unsigned long long lane_best(const float *wk, int lane) const
+    {
+        unsigned long long best = 0ull;
+        for (int c = lane; c < n + m; c += 64) {
+            bool av;
+            if (c < n) av = pairrow[c] < 0 && deg[c] == 1;
+            else av = cut(c - n) && pair[c - n] < 0;
+            if (av) {
+                const unsigned long long k = mts_key(wt(wk, c), c);
+                best = k > best ? k : best;
+            }
+        }
+        return best;
+    }
+
+    // Column-wise greedy search for the triangular set (Algorithm 7), exactly as stated:
+    // p times, take the degree-1 column with the largest key (weight, then lowest index)
+    // and eliminate the only row it still has. Wave 0 runs it: every lane keeps the best
+    // available column of the columns it owns (lbest), the wave takes the maximum, and the
+    // lanes of the eliminated row update the residual degrees of its columns. A lane whose
+    // best column was taken or lost its last row rescans its columns.
+    // Fills pair (column of each row), pairrow (row of each chosen standard column), order
+    // (rows in elimination order), lfv (forward-substitution level) and lbv
+    // (back-substitution level). Returns p.
     LPD_INLINE int mts(const float *wk)
     {
-        int *cnt = &sc->i[4];
         for (int i = tid; i < n; i += nt) {
+            const uint16_t *L = clist + (size_t)i * CW;
             int dg = 0;
-            for (int e = cd.colptr[i]; e < cd.colptr[i + 1]; ++e) dg += cut(cd.vlist[e] >> 5);
-            status[i] = dg;
+            for (int k = 0; k < CW && L[k] != kEnd; ++k) ++dg;
+            deg[i] = (uint8_t)dg;
             pairrow[i] = -1;
         }
         int pl = 0;
         for (int j = tid; j < m; j += nt) {
-            pair[j] = -1; rnd[j] = -1; lf[j] = -1; lb[j] = -1;
+            pair[j] = -1; lfv[j] = -1; lbv[j] = -1;
             pl += cut(j);
         }
-        if (tid == 0) *cnt = 0;
         pl = block_sum1(pl, sc);
         p = pl;
-        int round = 0;
-        // every round commits at least one row, so pl rounds always suffice
-        while (*cnt < pl && round <= pl) {
-            for (int j = tid; j < m; j += nt) {
-                if (!cut(j) || pair[j] >= 0) continue;
-                unsigned long long best = mts_key(wt(wk, n + j), n + j);
-                for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) {
-                    const int i = cd.col[e];
-                    if (status[i] == 1 && pairrow[i] < 0) {
-                        const unsigned long long k = mts_key(wt(wk, i), i);
-                        best = k > best ? k : best;
+        if (tid < 64) {
+            const int lane = tid;
+            lbest[lane] = lane_best(wk, lane);
+            ldirty[lane] = 0;
+            for (int step = 0; step < pl; ++step) {
+                __builtin_amdgcn_wave_barrier();
+                unsigned long long mine = lbest[lane];
+                if (ldirty[lane]) {
+                    mine = lane_best(wk, lane);
+                    lbest[lane] = mine;
+                    ldirty[lane] = 0;
+                }
+                const unsigned long long K = wave_max_u64(mine);
+                if (K == 0ull) break;   // no degree-1 column: cannot happen while rows remain
+                const int c = mts_key_col(K);
+                // the row of c: its only live row; the other rows give the forward level
+                int row, L = 0;
+                if (c >= n) {
+                    row = c - n;
+                } else {
+                    row = -1;
+                    const uint16_t *CL = clist + (size_t)c * CW;
+                    for (int k = 0; k < CW; ++k) {
+                        const uint16_t e = CL[k];
+                        if (e == kEnd) break;
+                        const int j = e_idx(e);
+                        if (pair[j] < 0) row = j;
+                        else L = max(L, (int)lfv[j] + 1);
+                    }
+                    if (row < 0) break;   // a degree-1 column always has its live row
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    pair[row] = (int16_t)c;
+                    lfv[row] = (int16_t)L;
+                    order[step] = (int16_t)row;
+                    if (c < n) pairrow[c] = (int16_t)row;
+                    ldirty[c & 63] = 1;
+                    ldirty[(n + row) & 63] = 1;
+                }
+                __builtin_amdgcn_wave_barrier();
+                // eliminate the row: its waiting columns lose one degree
+                if (lane < RW) {
+                    const uint16_t e = rlist[(size_t)row * RW + lane];
+                    if (e != kEnd) {
+                        const int i = e_idx(e);
+                        if (i != c && pairrow[i] < 0) {
+                            const int dgi = deg[i] - 1;
+                            deg[i] = (uint8_t)dgi;
+                            if (dgi == 1) atomicMax(&lbest[i & 63], mts_key(wt(wk, i), i));
+                            else if (dgi == 0) ldirty[i & 63] = 1;
+                        }
                     }
                 }
-                killkey[j] = best;
             }
-            if (tid == 0) sc->u64[0] = 0ull;
-            __syncthreads();
-            unsigned long long tau = 0ull;
-            for (int i = tid; i < n; i += nt) {
-                if (status[i] < 2 || pairrow[i] >= 0) continue;
-                // second smallest candidate key over the live rows = (rdeg-1)-th largest
-                unsigned long long k1 = ~0ull, k2 = ~0ull;
-                for (int e = cd.colptr[i]; e < cd.colptr[i + 1]; ++e) {
-                    const int j = cd.vlist[e] >> 5;
-                    if (!cut(j) || pair[j] >= 0) continue;
-                    const unsigned long long kk = killkey[j];
-                    if (kk < k1) { k2 = k1; k1 = kk; }
-                    else if (kk < k2) k2 = kk;
-                }
-                const unsigned long long own = mts_key(wt(wk, i), i);
-                const unsigned long long bv = k2 < own ? k2 : own;
-                tau = bv > tau ? bv : tau;
-            }
-            tau = wave_max(tau);
-            if ((tid & 63) == 0 && tau) atomicMax(&sc->u64[0], tau);
-            __syncthreads();
-            tau = sc->u64[0];
-            int ncom = 0;
-            for (int j = tid; j < m; j += nt) {
-                if (!cut(j) || pair[j] >= 0) continue;
-                const unsigned long long kk = killkey[j];
-                if (kk < tau) continue;
-                const int c = mts_key_col(kk);
-                pair[j] = c;
-                rnd[j] = round;
-                ++ncom;
+            __builtin_amdgcn_wave_barrier();
+            // back-substitution levels, rows in reverse elimination order: a row depends on
+            // the rows of the other chosen columns in it, all eliminated later
+            for (int step = pl - 1; step >= 0; --step) {
+                const int row = order[step], c = pair[row];
                 int L = 0;
-                if (c < n) {
-                    pairrow[c] = j;
-                    // the other rows of c were eliminated in earlier rounds
-                    for (int e = cd.colptr[c]; e < cd.colptr[c + 1]; ++e) {
-                        const int jj = cd.vlist[e] >> 5;
-                        if (jj != j && cut(jj)) L = max(L, lf[jj] + 1);
+                if (lane < RW) {
+                    const uint16_t e = rlist[(size_t)row * RW + lane];
+                    if (e != kEnd) {
+                        const int i = e_idx(e);
+                        if (i != c && pairrow[i] >= 0) L = lbv[pairrow[i]] + 1;
                     }
                 }
-                lf[j] = L;
-                // row j is eliminated: its other waiting columns lose one degree
-                for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) {
-                    const int i = cd.col[e];
-                    if (i != c && pairrow[i] < 0) atomicSub(&status[i], 1);
-                }
+                L = (int)wave_max_u32((uint32_t)L);
+                if (lane == 0) lbv[row] = (int16_t)L;
+                __builtin_amdgcn_wave_barrier();
             }
-            ncom = wave_sum(ncom);
-            if ((tid & 63) == 0 && ncom) atomicAdd(cnt, ncom);
-            __syncthreads();
-            ++round;
-        }
-        // back-substitution levels: a row depends on the rows of the other chosen columns in
-        // it, all of which were eliminated in later rounds
-        for (int rd = round - 1; rd >= 0; --rd) {
-            for (int j = tid; j < m; j += nt) {
-                if (rnd[j] != rd) continue;
-                const int c = pair[j];
-                int L = 0;
-                for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) {
-                    const int i = cd.col[e];
-                    if (i == c) continue;
-                    const int pr = pairrow[i];
-                    if (pr >= 0) L = max(L, lb[pr] + 1);
-                }
-                lb[j] = L;
-            }
-            __syncthreads();
-        }
-        return round;
-    }
-
-    // Rows grouped by level: blist holds the rows of back-substitution level L in
-    // [L ? boff[L-1] : 0, boff[L]), flist/foff likewise for forward substitution.
-    LPD_INLINE void build_levels()
-    {
-        int mb = -1, mf = -1;
-        for (int j = tid; j < m; j += nt) { mb = max(mb, lb[j]); mf = max(mf, lf[j]); }
-        mb = block_max_i(mb, sc);
-        mf = block_max_i(mf, sc);
-        nlb = mb + 1;
-        nlf = mf + 1;
-        for (int k = tid; k <= m; k += nt) { boff[k] = 0; foff[k] = 0; }
-        __syncthreads();
-        for (int j = tid; j < m; j += nt) {
-            if (lb[j] >= 0) atomicAdd(&boff[lb[j]], 1);
-            if (lf[j] >= 0) atomicAdd(&foff[lf[j]], 1);
-        }
-        block_exscan(boff, nlb);
-        block_exscan(foff, nlf);
-        for (int j = tid; j < m; j += nt) {
-            if (lb[j] >= 0) blist[atomicAdd(&boff[lb[j]], 1)] = j;
-            if (lf[j] >= 0) flist[atomicAdd(&foff[lf[j]], 1)] = j;
         }
         __syncthreads();
+        return pl;
     }
-
-    // ------------------------------------------------------------ triangular solves
-    // The preconditioning set M pairs every LP row j with one column pair[j]; A_M (rows by
-    // paired columns) is triangular after permutation with entries +-1 (Sec. V). Vectors over
-    // M's columns are stored at the row each column is paired with.
-    //
-    // Back-substitution out = A_M^-1 u: row j yields the value of its own column once the
-    // other M-columns in row j are known (levels lb ascending).
-    template <typename T, typename UF>
-    LPD_INLINE void back_sub(T *out, UF u_of_row)
-    {
-        for (int L = 0; L < nlb; ++L) {
-            const int k1 = boff[L];
-            for (int k = (L ? boff[L - 1] : 0) + tid; k < k1; k += nt) {
-                const int j = blist[k], c = pair[j];
-                const int e0 = cd.rowptr[j], e1 = cd.rowptr[j + 1];
-                T s = u_of_row(j);
-                int sgn = 1;
-                for (int e = e0; e < e1; ++e) {
-                    const int i = cd.col[e];
-                    const int a = aent(j, e - e0, i);
-                    if (i == c) { sgn = a; continue; }
-                    const int pr = pairrow[i];
-                    if (pr >= 0) s -= a > 0 ? out[pr] : -out[pr];
-                }
-                out[j] = sgn > 0 ? s : -s;
-            }
-            __syncthreads();
-        }
-    }
-
-    // Forward substitution out = A_M^-T e (out in row space): the row paired with column c
-    // is solved once the other rows of c are known (levels lf ascending).
-    template <typename T, typename EF>
-    LPD_INLINE void fwd_sub(T *out, EF e_of_row)
-    {
-        for (int L = 0; L < nlf; ++L) {
-            const int k1 = foff[L];
-            for (int k = (L ? foff[L - 1] : 0) + tid; k < k1; k += nt) {
-                const int j = flist[k], c = pair[j];
-                T s = e_of_row(j);
-                if (c < n) {
-                    int sgn = 1;
-                    for (int e = cd.colptr[c]; e < cd.colptr[c + 1]; ++e) {
-                        const int v = cd.vlist[e], jj = v >> 5;
-                        if (!cut(jj)) continue;
-                        const int a = aent(jj, v & 31, c);
-                        if (jj == j) { sgn = a; continue; }
-                        s -= a > 0 ? out[jj] : -out[jj];
-                    }
-                    s = sgn > 0 ? s : -s;
-                }
-                out[j] = s;
-            }
-            __syncthreads();
-        }
-    }
-
-    LPD_INLINE bool in_M(int c) const { return c < n ? pairrow[c] >= 0 : pair[c - n] == c; }
 
     // The slack columns as preconditioning set (A_M = I): used when Algorithm 7 is off.
     LPD_INLINE void slack_basis()
@@ -514,13 +558,129 @@ struct Frame {
         int pl = 0;
         for (int j = tid; j < m; j += nt) {
             const bool cj = cut(j);
-            pair[j] = cj ? n + j : -1;
-            lb[j] = cj ? 0 : -1;
-            lf[j] = cj ? 0 : -1;
+            pair[j] = cj ? (int16_t)(n + j) : (int16_t)-1;
+            lbv[j] = cj ? 0 : -1;
+            lfv[j] = cj ? 0 : -1;
             pl += cj;
         }
         p = block_sum1(pl, sc);
     }
+
+    // Rows grouped by level, each with its instruction list. Back-substitution level L holds
+    // slots [L ? boff[L-1] : 0, boff[L]) of bins (RW+1 entries per slot), forward level L
+    // slots [L ? foff[L-1] : 0, foff[L]) of fins (CW entries per slot). Slot header: the row
+    // and the sign of its diagonal entry. Back entries: the other M-columns of the row as
+    // references to their rows (coefficient negated), the columns outside M (the slack
+    // included) as column references. Forward entries: the other rows of the paired column
+    // (coefficient negated).
+    LPD_INLINE void build_levels()
+    {
+        int mb = -1, mf = -1;
+        for (int j = tid; j < m; j += nt) { mb = max(mb, (int)lbv[j]); mf = max(mf, (int)lfv[j]); }
+        mb = block_max_i(mb, sc);
+        mf = block_max_i(mf, sc);
+        nlb = mb + 1;
+        nlf = mf + 1;
+        for (int k = tid; k <= m; k += nt) { boff[k] = 0; foff[k] = 0; }
+        __syncthreads();
+        for (int j = tid; j < m; j += nt) {
+            if (lbv[j] >= 0) atomicAdd(&boff[lbv[j]], 1);
+            if (lfv[j] >= 0) atomicAdd(&foff[lfv[j]], 1);
+        }
+        block_exscan(boff, nlb);
+        block_exscan(foff, nlf);
+        for (int j = tid; j < m; j += nt) {
+            if (lbv[j] < 0) continue;
+            const int c = pair[j];
+            // back-substitution slot
+            {
+                uint16_t *B = bins + (size_t)atomicAdd(&boff[lbv[j]], 1) * (RW + 1);
+                const uint16_t *L = rlist + (size_t)j * RW;
+                bool dneg = false;
+                int q = 1;
+                for (int k = 0; k < RW; ++k) {
+                    const uint16_t e = L[k];
+                    if (e == kEnd) break;
+                    const int i = e_idx(e);
+                    if (i == c) { dneg = e_neg(e); continue; }
+                    if (pairrow[i] >= 0) B[q++] = enc(pairrow[i], !e_neg(e), true);
+                    else B[q++] = enc(i, e_neg(e), false);
+                }
+                if (c != n + j) B[q++] = enc(n + j, false, false);
+                for (; q <= RW; ++q) B[q] = kEnd;
+                B[0] = enc(j, dneg, false);
+            }
+            // forward-substitution slot
+            {
+                uint16_t *F = fins + (size_t)atomicAdd(&foff[lfv[j]], 1) * CW;
+                bool dneg = false;
+                int q = 1;
+                if (c < n) {
+                    const uint16_t *L = clist + (size_t)c * CW;
+                    for (int k = 0; k < CW; ++k) {
+                        const uint16_t e = L[k];
+                        if (e == kEnd) break;
+                        const int jj = e_idx(e);
+                        if (jj == j) { dneg = e_neg(e); continue; }
+                        F[q++] = enc(jj, !e_neg(e), true);
+                    }
+                }
+                for (; q < CW; ++q) F[q] = kEnd;
+                F[0] = enc(j, dneg, false);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ------------------------------------------------------------ triangular solves
+    // The preconditioning set M pairs every LP row j with one column pair[j]; A_M (rows by
+    // paired columns) is triangular after permutation with entries +-1 (Sec. V). Vectors over
+    // M's columns are stored at the row each column is paired with.
+    // Back-substitution out = A_M^-1 u (levels ascending).
+    template <typename T, typename UF>
+    LPD_INLINE void back_sub(T *out, UF u_of_row)
+    {
+        for (int L = 0; L < nlb; ++L) {
+            const int k1 = boff[L];
+            for (int k = (L ? boff[L - 1] : 0) + tid; k < k1; k += nt) {
+                const uint16_t *B = bins + (size_t)k * (RW + 1);
+                const uint16_t hd = B[0];
+                const int j = e_idx(hd);
+                T acc = u_of_row(j);
+                for (int q = 1; q <= RW; ++q) {
+                    const uint16_t e = B[q];
+                    if (e == kEnd) break;
+                    if (e_row(e)) acc += sgnv(e, out[e_idx(e)]);
+                }
+                out[j] = e_neg(hd) ? -acc : acc;
+            }
+            __syncthreads();
+        }
+    }
+
+    // Forward substitution out = A_M^-T e (out in row space; levels ascending).
+    template <typename T, typename EF>
+    LPD_INLINE void fwd_sub(T *out, EF e_of_row)
+    {
+        for (int L = 0; L < nlf; ++L) {
+            const int k1 = foff[L];
+            for (int k = (L ? foff[L - 1] : 0) + tid; k < k1; k += nt) {
+                const uint16_t *F = fins + (size_t)k * CW;
+                const uint16_t hd = F[0];
+                const int j = e_idx(hd);
+                T acc = e_of_row(j);
+                for (int q = 1; q < CW; ++q) {
+                    const uint16_t e = F[q];
+                    if (e == kEnd) break;
+                    acc += sgnv(e, out[e_idx(e)]);
+                }
+                out[j] = e_neg(hd) ? -acc : acc;
+            }
+            __syncthreads();
+        }
+    }
+
+    LPD_INLINE bool in_M(int c) const { return c < n ? pairrow[c] >= 0 : pair[c - n] == c; }
 
     // ------------------------------------------------------------ Algorithm 4
     // PCG on (A D^2 A^T) y = w with M = A_M D_M^2 A_M^T, applied in split form: with
@@ -557,8 +717,12 @@ struct Frame {
             fwd_sub<T>(V.s, [&](int j) { return V.h[j] * V.idm[j]; });
             // t = D_N^2 A_N^T s on the columns outside M
             for (int c = tid; c < n + m; c += nt) {
-                if (!colpresent(c) || in_M(c)) continue;
-                V.t[c] = V.dsq[c] * (c < n ? col_dot<T>(c, V.s) : V.s[c - n]);
+                if (c < n) {
+                    if (pairrow[c] < 0) V.t[c] = V.dsq[c] * col_dot<T>(c, V.s);
+                } else {
+                    const int j = c - n;
+                    if (cut(j) && pair[j] != c) V.t[c] = V.dsq[c] * V.s[j];
+                }
             }
             __syncthreads();
             // f = A_M^-1 (A_N t) over s; l = h + D_M^-1 f
@@ -566,19 +730,16 @@ struct Frame {
             for (int L = 0; L < nlb; ++L) {
                 const int k1 = boff[L];
                 for (int k = (L ? boff[L - 1] : 0) + tid; k < k1; k += nt) {
-                    const int j = blist[k], c = pair[j];
-                    const int e0 = cd.rowptr[j], e1 = cd.rowptr[j + 1];
-                    T acc = c == n + j ? (T)0 : V.t[n + j];
-                    int sgn = 1;
-                    for (int e = e0; e < e1; ++e) {
-                        const int i = cd.col[e];
-                        const int a = aent(j, e - e0, i);
-                        if (i == c) { sgn = a; continue; }
-                        const int pr = pairrow[i];
-                        if (pr >= 0) acc -= a > 0 ? V.s[pr] : -V.s[pr];
-                        else acc += a > 0 ? V.t[i] : -V.t[i];
+                    const uint16_t *B = bins + (size_t)k * (RW + 1);
+                    const uint16_t hd = B[0];
+                    const int j = e_idx(hd);
+                    T acc = 0;
+                    for (int q = 1; q <= RW; ++q) {
+                        const uint16_t e = B[q];
+                        if (e == kEnd) break;
+                        acc += sgnv(e, e_row(e) ? V.s[e_idx(e)] : V.t[e_idx(e)]);
                     }
-                    const T fj = sgn > 0 ? acc : -acc;
+                    const T fj = e_neg(hd) ? -acc : acc;
                     V.s[j] = fj;
                     const T lj = V.h[j] + fj * V.idm[j];
                     V.l[j] = lj;
@@ -654,13 +815,14 @@ struct Frame {
         double nr2 = 0.0;
         for (int j = tid; j < m; j += nt) {
             if (!cut(j)) continue;
-            const int e0 = cd.rowptr[j], e1 = cd.rowptr[j + 1];
-            double s = d2[n + j] * dy[j];
-            for (int e = e0; e < e1; ++e) {
-                const int i = cd.col[e];
-                s += aent(j, e - e0, i) > 0 ? tq[i] : -tq[i];
+            const uint16_t *L = rlist + (size_t)j * RW;
+            double acc = d2[n + j] * dy[j];
+            for (int k = 0; k < RW; ++k) {
+                const uint16_t e = L[k];
+                if (e == kEnd) break;
+                acc += sgnv(e, tq[e_idx(e)]);
             }
-            const double rj = w[j] - s;
+            const double rj = w[j] - acc;
             rho[j] = rj;
             nr2 += rj * rj;
         }
@@ -697,7 +859,7 @@ struct Frame {
         }
         const bool use_xi = mu > 0.0;
         const double xi_goal = o.xi_tol * mu;
-        CG<PT> V1 = {r, yv, h, l, zz, t, idm, om, d2f};
+        CG<PT> V1 = {r, v, h, l, s, t, idm, om, d2f};
         CG<double> V2 = {c64[0], c64[1], c64[2], c64[3], c64[4], tq, c64[5], c64[6], d2};
         const double tol1 = sizeof(PT) == 8 ? (o.ref_tol < o.pcg_tol ? o.ref_tol : o.pcg_tol) : o.pcg_tol;
         const double tol2 = o.ref_tol < o.pcg_tol ? o.ref_tol : o.pcg_tol;
@@ -709,8 +871,7 @@ struct Frame {
             double nr2 = residual64();
             double err = use_xi ? xi_max() : nr2;
             if (!(err < prev)) {
-                // undo the round: its correction is the forward substitution left in f64 only
-                // when mu = 0, so recompute it from the stored dy difference
+                // undo the round
                 for (int j = tid; j < m; j += nt)
                     if (cut(j)) dy[j] = c64[7][j];
                 __syncthreads();
@@ -738,8 +899,8 @@ struct Frame {
 
     LPD_INLINE void set_d2f(int c, double dd)
     {
-        double v = dd < 1e-30 ? 1e-30 : (dd > 1e30 ? 1e30 : dd);
-        d2f[c] = (PT)v;
+        const double vv = dd < 1e-30 ? 1e-30 : (dd > 1e30 ? 1e30 : dd);
+        d2f[c] = (PT)vv;
     }
 
     // ------------------------------------------------------------ interior-point method
@@ -750,10 +911,11 @@ struct Frame {
     // dz = X^-1 (r_e - Z dx); separate primal and dual step lengths (fraction eta of the
     // distance to the boundary, at most 1). Starts at x = e, y = 0, z = e; stops when
     // x^T z / (1 + |c^T x|), ||r_b|| / (1 + ||b||) and ||r_c|| / (1 + ||c||) are all < eps.
-    // Returns 0 or a negative LPDEC_FLAG_*.
+    // The LP's row and column lists must be built. Returns 0 or a negative LPDEC_FLAG_*.
     LPD_INLINE int ipm(lpdec_stats &st, int &iters)
     {
         double a0[2] = {0.0, 0.0};
+        int pl = 0;
         for (int j = tid; j < m; j += nt) {
             if (cut(j)) {
                 // b of the flipped parity inequality: |V| - 1 - sum of its u-coefficients
@@ -762,14 +924,15 @@ struct Frame {
                 const int e0 = cd.rowptr[j], e1 = cd.rowptr[j + 1];
                 int vsz = 0, sneg = 0;
                 for (int e = e0; e < e1; ++e) {
-                    const int s = ((V >> (e - e0)) & 1u) ? 1 : -1;
-                    vsz += s > 0;
-                    if (sg[cd.col[e]] < 0) sneg += s;
+                    const int sv = ((V >> (e - e0)) & 1u) ? 1 : -1;
+                    vsz += sv > 0;
+                    if (sg[cd.col[e]] < 0) sneg += sv;
                 }
                 const double bj = (double)(vsz - 1 - sneg);
                 b[j] = bj;
                 a0[0] += bj * bj;
                 x[n + j] = 1.0; z[n + j] = 1.0;
+                ++pl;
             } else {
                 b[j] = 0.0; x[n + j] = 0.0; z[n + j] = 0.0;
             }
@@ -780,6 +943,7 @@ struct Frame {
             a0[1] += g[i] * g[i];
         }
         block_sum<2>(a0, sc);
+        p = block_sum1(pl, sc);
         const double nb = sqrt(a0[0]), nc = sqrt(a0[1]);
         const double q = (double)(n + p);
         int status = LPDEC_FLAG_IPM_CAP, it;
@@ -825,7 +989,7 @@ struct Frame {
                 if (cut(j)) w[j] = rb[j] + row_dot<double>(j, tq);
             // preconditioner for this iteration (Sec. V-B: found anew at every iteration)
             const long long t0 = wall_clock64();
-            if (o.precond) st.mts_rounds += mts(nullptr);
+            if (o.precond) mts(nullptr);
             else slack_basis();
             build_levels();
             st.max_levels = max(st.max_levels, max(nlb, nlf));
@@ -835,6 +999,7 @@ struct Frame {
             const long long t2 = wall_clock64();
             st.ticks_mts += t1 - t0;
             st.ticks_solve += t2 - t1;
+            st.mts_rounds += o.precond ? p : 0;
             st.pcg_iters += pits;
             st.pcg_rows += (long long)pits * p;
             st.ipm_cols += n + p;
@@ -908,10 +1073,8 @@ struct Frame {
             if (!added) break;
             if (a.trace && k < a.trace_cap)
                 for (int j = tid; j < m; j += nt) a.trace[((size_t)f * a.trace_cap + k) * m + j] = vmask[j];
+            build_lists();
             int its = 0;
-            int pl = 0;
-            for (int j = tid; j < m; j += nt) pl += cut(j);
-            p = block_sum1(pl, sc);
             status = ipm(st, its);
             st.malp_iters++;
             st.ipm_iters += its;
@@ -934,7 +1097,7 @@ struct Frame {
             fr = d > fr ? d : fr;
             ob += g[i] * ui;
             const int xh = fabs(ui - 0.5) <= o.tau_int ? (g[i] >= 0.0 ? 0 : 1) : (ui > 0.5 ? 1 : 0);
-            status_xh(i, xh);
+            deg[i] = (uint8_t)xh;   // the decisions, kept for the syndrome
             a.xhat[(size_t)f * n + i] = (uint8_t)xh;
             if (a.u_out) a.u_out[(size_t)f * n + i] = ui;
         }
@@ -943,7 +1106,7 @@ struct Frame {
         int syn = 0;
         for (int j = tid; j < m; j += nt) {
             int par = 0;
-            for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) par ^= this->status[cd.col[e]];
+            for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) par ^= deg[cd.col[e]];
             syn |= par;
         }
         syn = block_or(syn, sc);
@@ -960,9 +1123,6 @@ struct Frame {
             if (a.stats) a.stats[f] = st;
         }
     }
-
-    // the decision bits are kept in the residual-degree array for the syndrome
-    LPD_INLINE void status_xh(int i, int v) { this->status[i] = v; }
 };
 
 }  // namespace lpdec

@@ -15,9 +15,8 @@ LPD_INLINE void run_ipm(Frame<PT> &F, const Args &a, int f)
     const int m = F.m, n = F.n;
     F.load_gamma(a, f);
     for (int j = F.tid; j < m; j += F.nt) F.vmask[j] = a.vmask_in[(size_t)f * m + j];
-    int pl = 0;
-    for (int j = F.tid; j < m; j += F.nt) pl += a.vmask_in[(size_t)f * m + j] != 0u;
-    F.p = block_sum1(pl, F.sc);
+    __syncthreads();
+    F.build_lists();
     lpdec_stats st = {};
     int its = 0;
     const int status = F.ipm(st, its);
@@ -50,9 +49,8 @@ LPD_INLINE void run_solve(Frame<PT> &F, const Args &a, int f)
         F.d2[c] = dd;
         F.set_d2f(c, dd);
     }
-    int pl = 0;
-    for (int j = F.tid; j < m; j += F.nt) pl += a.vmask_in[(size_t)f * m + j] != 0u;
-    F.p = block_sum1(pl, F.sc);
+    __syncthreads();
+    F.build_lists();
     if (F.o.precond) F.mts(nullptr);
     else F.slack_basis();
     F.build_levels();
@@ -78,21 +76,12 @@ LPD_INLINE void run_matvec(Frame<PT> &F, const Args &a, int f)
     }
     for (int c = F.tid; c < n + m; c += F.nt) F.d2f[c] = (PT)a.d2_in[f * q + c];
     __syncthreads();
+    F.build_lists();
     for (int i = F.tid; i < n; i += F.nt) F.t[i] = F.d2f[i] * F.template col_dot<PT>(i, F.h);
+    for (int j = F.tid; j < m; j += F.nt) F.t[n + j] = F.d2f[n + j] * F.h[j];
     __syncthreads();
-    for (int j = F.tid; j < m; j += F.nt) {
-        double out = 0.0;
-        if (F.cut(j)) {
-            const int e0 = F.cd.rowptr[j], e1 = F.cd.rowptr[j + 1];
-            PT s = F.d2f[n + j] * F.h[j];
-            for (int e = e0; e < e1; ++e) {
-                const int i = F.cd.col[e];
-                s += F.aent(j, e - e0, i) > 0 ? F.t[i] : -F.t[i];
-            }
-            out = (double)s;
-        }
-        a.vec_out[(size_t)f * m + j] = out;
-    }
+    for (int j = F.tid; j < m; j += F.nt)
+        a.vec_out[(size_t)f * m + j] = F.cut(j) ? (double)F.template row_dot<PT>(j, F.t) : 0.0;
 }
 
 template <typename PT>
@@ -100,14 +89,16 @@ LPD_INLINE void run_mts(Frame<PT> &F, const Args &a, int f)
 {
     const int m = F.m, n = F.n;
     for (int j = F.tid; j < m; j += F.nt) F.vmask[j] = a.hascut_in[(size_t)f * m + j] ? 1u : 0u;
+    for (int i = F.tid; i < n; i += F.nt) F.sg[i] = 1;
     __syncthreads();
-    const int rounds = F.mts(a.w_in + (size_t)f * (n + m));
+    F.build_lists();
+    F.mts(a.w_in + (size_t)f * (n + m));
     for (int j = F.tid; j < m; j += F.nt) {
         a.i_out[(size_t)f * m + j] = F.pair[j];
-        a.i_out2[(size_t)f * m + j] = F.lb[j];
-        a.i_out3[(size_t)f * m + j] = F.lf[j];
+        a.i_out2[(size_t)f * m + j] = F.lbv[j];
+        a.i_out3[(size_t)f * m + j] = F.lfv[j];
     }
-    if (F.tid == 0 && a.flag) a.flag[f] = rounds;
+    if (F.tid == 0 && a.flag) a.flag[f] = F.p;
 }
 
 template <typename PT>
@@ -119,15 +110,15 @@ LPD_INLINE void run_cuts(Frame<PT> &F, const Args &a, int f)
     for (int j = F.tid; j < m; j += F.nt) {
         uint32_t V;
         double lhs;
-        const int v = F.find_cut(j, V, lhs);
+        const int vv = F.find_cut(j, V, lhs);
         a.u32_out[(size_t)f * m + j] = V;
-        a.u8_out[(size_t)f * m + j] = (uint8_t)v;
+        a.u8_out[(size_t)f * m + j] = (uint8_t)vv;
         if (a.vec_out) a.vec_out[(size_t)f * m + j] = lhs;
     }
 }
 
 template <typename PT, bool HOT_LDS, int MODE>
-__global__ void __launch_bounds__(1024) lpdec_main(Args a)
+__global__ void __launch_bounds__(256) lpdec_main(Args a)
 {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Scratch sc;
