@@ -39,7 +39,7 @@ def workload():
 
 
 def algorithmic_bytes(st, n):
-    """Bytes the method must move per frame (see DESIGN.md): per PCG iteration 27p + 4q
+    """Bytes the method must move per frame: per PCG iteration 27p + 4q
     (q = n + p, FP32 vectors), per interior-point iteration 120q (FP64 vector passes)."""
     pcg_rows = st["pcg_rows"].astype(np.float64)
     pcg_its = st["pcg_iters"].astype(np.float64)
@@ -153,7 +153,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: frames are independent LPs and the "
-                                   "multi-GPU form is a per-frame shard with no exchange (see DESIGN.md); "
+                                   "multi-GPU form is a per-frame shard with no exchange; "
                                    "run with --gpus 1"}))
         sys.exit(2)
 
@@ -236,7 +236,7 @@ def main():
         res["cpu_baseline"] = cb
         mism = [k for k, (t, xh, fl, ob) in done
                 if not (np.array_equal(xh, xhat[k]) and fl == flags[k]
-                        and abs(ob - objs[k]) <= 1e-6 * max(1.0, abs(ob)))]
+                        and abs(ob - objs[k]) <= 1e-6 * (1.0 + abs(ob - float(G[k][G[k] < 0].sum()))))]
         res["parity_sample"] = {"frames": len(done), "mismatches": len(mism)}
     if args.serve:
         res["serving"] = serving(ctx)

@@ -23,7 +23,9 @@
  * Readings where the paper is silent (all documented in the design notes):
  *   mu = sigma_c * x^T z / q with sigma_c = 0.1; fraction-to-boundary steps with eta = 0.9995;
  *   start x = e, y = 0, z = e; stop when x^T z/(1+|c^T x|), ||r_b||/(1+||b||) and
- *   ||r_c||/(1+||c||) are all below eps (1e-8); a cut is violated when its left-hand side is
+ *   ||r_c||/(1+||c||) are all below eps (1e-8), or, once the largest of the three is below
+ *   eps_stall (1e-7), when it has not at least halved over the last two iterations (the
+ *   numerical floor of a degenerate LP in double precision); a cut is violated when its left-hand side is
  *   below 1 - tau_viol; a cut is inactive when its slack exceeds max(tau_act, its dual slack);
  *   u_i > 1/2 strict in Algorithm 2 and argmin ties go to the lowest variable index;
  *   Algorithm 7 orders columns by (float(d_i^2) descending, column index ascending), slack
@@ -44,6 +46,7 @@ typedef struct {
     double sigma_c;  /* centering factor of mu */
     double eta;      /* fraction-to-boundary factor */
     double eps;      /* IPM termination tolerance */
+    double eps_stall;/* below it, an iteration that makes no progress ends the IPM */
 } orc_opts;
 
 typedef struct {
@@ -292,6 +295,7 @@ static int ipm_solve(const lp_t *lp, const orc_opts *o, double *x, double *y, do
     double *Q = malloc(sizeof(double) * ((size_t)p * p + 1));
     double nb = norm2(lp->b, p), nc = norm2(lp->c, q);
     int it, status = -1;
+    double phi1 = INFINITY, phi2 = INFINITY;   /* error measure one and two iterations ago */
     for (it = 0; it < o->ipm_max; ++it) {
         lp_Ax(lp, x, rb);
         for (int r = 0; r < p; ++r) rb[r] = lp->b[r] - rb[r];
@@ -300,8 +304,14 @@ static int ipm_solve(const lp_t *lp, const orc_opts *o, double *x, double *y, do
         double gap = dot(x, z, q);
         double cx = dot(lp->c, x, q);
         if (!isfinite(gap) || !isfinite(cx)) { status = -2; break; }
-        if (gap / (1.0 + fabs(cx)) < o->eps && norm2(rb, p) / (1.0 + nb) < o->eps &&
-            norm2(rc, q) / (1.0 + nc) < o->eps) { status = 0; break; }
+        double e1 = gap / (1.0 + fabs(cx)), e2 = norm2(rb, p) / (1.0 + nb);
+        double e3 = norm2(rc, q) / (1.0 + nc);
+        double phi = fmax(e1, fmax(e2, e3));
+        if (phi < o->eps) { status = 0; break; }
+        /* stalled at the floor of double precision: accept the iterate */
+        if (phi < o->eps_stall && phi > 0.5 * phi2) { status = 0; break; }
+        phi2 = phi1;
+        phi1 = phi;
         double mu = o->sigma_c * gap / q;
         newton(lp, x, y, z, mu, dx, dy, dz, rb, rc, Q, t1, t2);
         double bp = 1.0, bd = 1.0;

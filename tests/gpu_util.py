@@ -22,8 +22,14 @@ def make_ctx(**opts):
     return c
 
 
-def obj_close(a, b, rel=1e-6):
-    return abs(a - b) <= rel * max(1.0, abs(b))
+def obj_close(a, b, gamma, rel=1e-6):
+    """LP objectives gamma^T u agree to `rel` relative to the scale on which the interior-point
+    method measures its duality gap, 1 + c^T x with c = |gamma| and x the flipped variables
+    (c^T x = gamma^T u - sum of the negative gamma_i). A relative test against |gamma^T u|
+    alone is meaningless near gamma^T u = 0, the value of every correctly decoded frame."""
+    g = np.asarray(gamma, dtype=np.float64)
+    scale = 1.0 + abs(b - float(g[g < 0].sum()))
+    return abs(a - b) <= rel * scale
 
 
 def snapshot_d2(orc, code, gamma, masks, ipm_iter):

@@ -8,7 +8,7 @@ import pytest
 
 from synth.channel import awgn_llr, frame_seed
 from synth.codes import regular_code, irregular_code
-from tests.gpu_util import cuda, host, make_ctx, snapshot_d2
+from tests.gpu_util import cuda, host, make_ctx, obj_close, snapshot_d2
 
 pytestmark = pytest.mark.gpu
 
@@ -201,5 +201,5 @@ def test_ipm_matches_oracle(ctx, orc, precision):
         rc, xo, yo, zo, ito = orc.ipm(code, G[f], M[f])
         u_g = np.where(G[f] >= 0, x[f, :code.n], 1 - x[f, :code.n])
         u_o = np.where(G[f] >= 0, xo[:code.n], 1 - xo[:code.n])
-        assert abs(G[f] @ u_g - G[f] @ u_o) <= 1e-6 * max(1, abs(G[f] @ u_o))
+        assert obj_close(G[f] @ u_g, G[f] @ u_o, G[f])
         assert np.abs(u_g - u_o).max() < 1e-4

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from synth.channel import awgn_llr, bsc_llr, frame_seed
+from synth.channel import awgn_llr, batch_awgn, bsc_llr, frame_seed
 from synth.codes import from_dense, irregular_code, regular_code
 from tests import refs
 
@@ -425,3 +425,21 @@ def test_pcg_exact_preconditioner_one_iteration(orc):
         y, it, res = orc.pcg(code, gamma, masks, d2, w, tol=1e-10, maxit=50)
         assert it == 1 and res[-1] < 1e-10
     assert hits >= 3
+
+
+def test_stalled_ipm_floor_rule(orc):
+    """Reading of the termination test: on degenerate LPs the plain normal equations stall near
+    a relative gap of 1e-8 in FP64. Frames of the n=1024 batch (Eb/N0 1.5 dB, FP32 LLRs) whose
+    last LP stalls there hit the iteration cap without the floor rule; with it they end at the
+    LP-decoding optimum, checked against HiGHS on the full relaxation (Theorem 2c)."""
+    code = regular_code(1024)
+    G = batch_awgn(code.n, 0.5, 1.5, 54, stream=2024, snr_index=0).astype(np.float32)
+    for f in (8, 53):
+        gamma = G[f].astype(np.float64)
+        stuck = orc.decode(code, gamma, orc.OracleOpts(eps_stall=0.0))
+        assert stuck.flag == -1                       # the 1e-8 target alone is not reachable
+        res = orc.decode(code, gamma)
+        assert res.status == 0 and res.flag in (0, 1)
+        fun, _ = refs.feldman_lp(code, gamma)
+        scale = 1.0 + abs(fun - gamma[gamma < 0].sum())
+        assert abs(res.objective - fun) <= 1e-7 * scale
