@@ -141,14 +141,66 @@ def serving(ctx, seconds=20.0, qps=None, seed=5):
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
 
+def sources_digest():
+    """SHA-256 over the HIP sources and the C header: identifies the kernel build that a
+    stored traffic measurement belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0902_0657_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files + [os.path.join(ROOT, "include", "lpdec.h")]:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lpdec_main_n1024_traffic.md")
+
+
+def stored_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when it was taken on
+    the current sources (else None). The summary holds one JSON line starting with
+    '{"traffic"'."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    with open(TRAFFIC_FILE) as fh:
+        rec = [json.loads(line) for line in fh if line.startswith('{"traffic"')]
+    if not rec:
+        return None, "no counter summary"
+    t = rec[-1]["traffic"]
+    if t.get("sources_sha256") != sources_digest():
+        return None, "kernel changed since the counters were taken"
+    fetch = t["fetch_kib_per_launch"] * 1024.0 * t["fetch_scale"]
+    write = t["write_kib_per_launch"] * 1024.0 * t["write_scale"]
+    return fetch + write, "FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors"
+
+
+def copy_calibration(dev, nbytes=256 << 20):
+    """One plain device-to-device copy of known size, for scaling the HBM counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nbytes} bytes read and written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp64",
+                    help="PCG vector precision of the main leg (fp64: the library's batch default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-PCG leg")
     ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 256 MiB copy first (HBM counter calibration under rocprofv3)")
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,23 +215,30 @@ def main():
         from paper_0902_0657_amd import build as B
         B.build()
     code, G = workload()
+    dev = torch.device("cuda:0")
+    if args.calib_copy:
+        copy_calibration(dev)
     ctx = Context(0)
     if args.block:
         ctx.set_option("BLOCK", args.block)
+    fp64 = args.precision == "fp64"
+    ctx.set_option("PRECISION", 1 if fp64 else 0)
     C = Code.from_synth(ctx, code)
-    dev = torch.device("cuda:0")
     g = torch.as_tensor(G, device=dev)
     stream = torch.cuda.current_stream(dev)
-    out = None
-    for w in range(max(1, args.warmup)):
-        out = ctx.decode_batch(C, g, out=out)
+    nf = G.shape[0]
+    out = ctx.batch_outputs(C, nf, dev)
+    for w in range(args.warmup):
+        ctx.decode_batch(C, g, out=out)
         torch.cuda.synchronize()
         log(f"warmup {w + 1} done")
+    # HIP events on the stream the decode kernel is launched on
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(args.steps):
-        ctx.decode_batch(C, g, out=out)
+        ctx.decode_batch(C, g, out=out, stream=stream)
         ev[k + 1].record(stream)
         ev[k + 1].synchronize()
         log(f"step {k + 1}: {ev[k].elapsed_time(ev[k + 1]):.1f} ms")
@@ -187,7 +246,6 @@ def main():
     wall = time.perf_counter() - t0
     step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     total_s = float(step_ms.sum()) / 1e3
-    nf = G.shape[0]
     value = nf * args.steps / total_s
     st = stats_table(out["stats"])
     flags = out["flag"].cpu().numpy()
@@ -196,17 +254,22 @@ def main():
     alg = algorithmic_bytes(st, code.n)
     kern_s = float(step_ms.mean()) / 1e3
     achieved = alg / kern_s / 1e9
+    traffic, traffic_note = stored_traffic()
+    frame_ms = st["ticks_total"].astype(np.float64) / 1e5   # 100 MHz device clock
     res = {
         "metric": "LP-decoded frames/s at n=1024 (3,6) + p50/p99 latency, vs plain FP64 GPU",
         "value": value, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": float(step_ms.mean()), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 PCG / f64 IPM", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if fp64 else "f32 PCG / f64 IPM", "data": "synthetic",
         "config": {"workload": "(3,6)-regular LDPC n=1024 m=512, AWGN Eb/N0 1.5/2.0/2.5 dB "
                                "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
-                               "FP32 PCG tol 1e-6 + FP64 refinement",
+                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " with FP64 refinement",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "note": "batch mode: every frame of a launch completes with the launch"},
+                       "note": "batch mode: a frame's result is available when its launch ends"},
+        "frame_decode_ms": {"p50": float(np.percentile(frame_ms, 50)), "p99": float(np.percentile(frame_ms, 99)),
+                            "max": float(frame_ms.max()),
+                            "note": "in-kernel decode time of each frame (device clock)"},
         "wall_s_timed": wall,
         "decode_stats": {"flags": {str(k): int(v) for k, v in zip(*np.unique(flags, return_counts=True))},
                          "mean_malp_iters": float(st["malp_iters"].mean()),
@@ -214,14 +277,34 @@ def main():
                          "mean_pcg_iters": float(st["pcg_iters"].mean()),
                          "mean_pcg_per_newton": float(st["pcg_iters"].sum() / max(1, st["ipm_iters"].sum())),
                          "max_p": int(st["p_max"].max()), "max_levels": int(st["max_levels"].max()),
-                         "mean_mts_rounds_per_ipm": float(st["mts_rounds"].sum() / max(1, st["ipm_iters"].sum())),
+                         "pcg_us_per_iteration": float(st["ticks_pcg"].sum() / 100.0 / max(1, st["pcg_iters"].sum())),
+                         "mts_us_per_ipm_iteration": float(st["ticks_mts"].sum() / 100.0 / max(1, st["ipm_iters"].sum())),
                          "ref_rounds": int(st["ref_rounds"].sum())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "lpdec_main<float, LDS, DECODE>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,
+                     "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
+                     "kernel": f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>",
                      "algorithmic_bytes_per_launch": alg, "kernel_ms": kern_s * 1e3},
     }
-    plain_res, cpu_res = None, None
+    if not args.no_fp32 and fp64:
+        c32 = Context(0)
+        c32.set_option("PRECISION", 0)
+        C32 = Code.from_synth(c32, code)
+        o32 = c32.batch_outputs(C32, nf, dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c32.decode_batch(C32, g, out=o32, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms32 = e0.elapsed_time(e1)
+        f32, x32 = o32["flag"].cpu().numpy(), o32["xhat"].cpu().numpy()
+        res["fp32_pcg"] = {"value": nf / (ms32 / 1e3), "unit": "frames/s", "ms_per_step": ms32,
+                           "flags": {str(k): int(v) for k, v in zip(*np.unique(f32, return_counts=True))},
+                           "differs_from_main": int(sum(1 for f in range(nf) if f32[f] != flags[f]
+                                                        or not np.array_equal(x32[f], xhat[f])))}
+        log(f"fp32 PCG leg: {ms32:.1f} ms")
+        c32.close()
     if not args.no_plain:
         frames = [g0 + k for k in range(8) for g0 in (0, 171, 342)]
         pf, plain_res = plain_fp64(ctx, C, G, frames)

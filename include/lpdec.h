@@ -16,8 +16,8 @@
  *     failure of a context. A numerical failure of one frame is NOT an API error: it is
  *     reported in that frame's flag (< 0).
  *   - H is given in CSR form: rows = checks (m), columns = variables (n), 0-based, column
- *     indices strictly increasing within a row, no empty row, row degree <= 32,
- *     m + n <= 16383. The library copies H; the caller keeps ownership of its arrays.
+ *     indices strictly increasing within a row, no empty row, row degree <= 15, column
+ *     degree <= 16, m + n <= 16383. The library copies H; the caller keeps ownership of its arrays.
  *   - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory of the
  *     context's device (for example torch CUDA tensors), owned by the caller.
  *   - Batched layouts are frame-major: element i of frame f of an n-vector is at f*n + i.
@@ -75,6 +75,7 @@ typedef struct {
     int64_t ticks_mts;    /* device clock ticks (100 MHz) in the triangular-set search */
     int64_t ticks_solve;  /* ticks in the Newton solves (PCG, refinement) */
     int64_t ticks_total;  /* ticks of the whole decode of the frame */
+    int64_t ticks_pcg;    /* ticks inside PCG iterations (part of ticks_solve) */
 } lpdec_stats;
 
 /* ---- context ---------------------------------------------------------------------- */
@@ -86,9 +87,12 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
 
 /* Options (key, value). Values are converted to the key's type.
  *   MALP_MODE      0 = MALP-A (Algorithm 3), 1 = MALP-B (all inactive cuts removed first)
- *   PRECISION      0 = FP32 PCG with FP64 refinement of dy (default for batches),
- *                  1 = FP64 everywhere (the plain form; default for lpdec_decode)
- *                  -1 = per call default (lpdec_decode FP64, batches FP32)
+ *   PRECISION      1 = FP64 PCG vectors (default): the hot path is latency-bound, so FP32
+ *                  vectors cost the same per PCG iteration and need several times more
+ *                  iterations on the ill-conditioned late Newton systems;
+ *                  0 = FP32 PCG vectors with FP64 refinement of dy (a solve whose FP32
+ *                  rounds stall continues with FP64 vectors in global memory);
+ *                  -1 = the default
  *   TAU_VIOL       a cut is violated when its left-hand side is below 1 - TAU_VIOL (1e-4)
  *   TAU_ACT        a cut is inactive when its slack exceeds max(TAU_ACT, dual slack) (1e-4)
  *   TAU_INT        integrality threshold of the output (1e-4)
@@ -106,12 +110,16 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  preconditioning set (a diagonal preconditioner)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.1)
+ *   IPM_STALL      once the largest of the three IPM error measures is below IPM_STALL but
+ *                  has not at least halved over the last two iterations, the LP counts as
+ *                  solved (the double-precision floor of a degenerate LP) (1e-7)
  */
 enum {
     LPDEC_OPT_MALP_MODE = 0, LPDEC_OPT_PRECISION, LPDEC_OPT_TAU_VIOL, LPDEC_OPT_TAU_ACT,
     LPDEC_OPT_TAU_INT, LPDEC_OPT_IPM_EPS, LPDEC_OPT_SIGMA, LPDEC_OPT_ETA, LPDEC_OPT_PCG_TOL,
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
-    LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL, LPDEC_OPT__COUNT
+    LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
+    LPDEC_OPT_IPM_STALL, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);

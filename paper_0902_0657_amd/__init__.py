@@ -94,6 +94,21 @@ class Context:
                                         C.byref(st), u.ctypes.data_as(C.c_void_p)))
         return xhat, int(flag.value), float(obj.value), {f: getattr(st, f) for f in STATS_FIELDS}, u
 
+    @staticmethod
+    def batch_outputs(code: "Code", nf, device, want_u=False, want_stats=True):
+        """Output tensors of decode_batch for nf frames (allocated, not filled)."""
+        import torch
+        out = {
+            "xhat": torch.empty((nf, code.n), dtype=torch.uint8, device=device),
+            "flag": torch.empty(nf, dtype=torch.int32, device=device),
+            "obj": torch.empty(nf, dtype=torch.float64, device=device),
+        }
+        if want_stats:
+            out["stats"] = torch.empty((nf, STATS_WORDS), dtype=torch.int32, device=device)
+        if want_u:
+            out["u"] = torch.empty((nf, code.n), dtype=torch.float64, device=device)
+        return out
+
     def decode_batch(self, code: "Code", gamma, out=None, want_u=False, want_stats=True, stream=None):
         """gamma: CUDA tensor [nframes, n] (float32 or float64). Asynchronous on `stream`
         (default: torch's current stream). Returns a dict of output tensors."""
@@ -102,15 +117,7 @@ class Context:
         nf = gamma.shape[0]
         dev = gamma.device
         if out is None:
-            out = {
-                "xhat": torch.empty((nf, code.n), dtype=torch.uint8, device=dev),
-                "flag": torch.empty(nf, dtype=torch.int32, device=dev),
-                "obj": torch.empty(nf, dtype=torch.float64, device=dev),
-            }
-            if want_stats:
-                out["stats"] = torch.empty((nf, STATS_WORDS), dtype=torch.int32, device=dev)
-            if want_u:
-                out["u"] = torch.empty((nf, code.n), dtype=torch.float64, device=dev)
+            out = self.batch_outputs(code, nf, dev, want_u=want_u, want_stats=want_stats)
         gdt = 1 if gamma.dtype == torch.float64 else 0
         assert gamma.dtype in (torch.float32, torch.float64)
         s = stream if stream is not None else torch.cuda.current_stream(dev)

@@ -13,7 +13,7 @@ FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT = -1, -2, -3, -4
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",
-    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL"])}
+    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL"])}
 
 
 class Stats(C.Structure):
@@ -22,7 +22,7 @@ class Stats(C.Structure):
                 ("max_levels", C.c_int32), ("status", C.c_int32), ("escalations", C.c_int32),
                 ("reserved", C.c_int32), ("pcg_rows", C.c_int64),
                 ("ipm_cols", C.c_int64), ("ticks_mts", C.c_int64), ("ticks_solve", C.c_int64),
-                ("ticks_total", C.c_int64)]
+                ("ticks_total", C.c_int64), ("ticks_pcg", C.c_int64)]
 
 
 STATS_FIELDS = [f[0] for f in Stats._fields_]

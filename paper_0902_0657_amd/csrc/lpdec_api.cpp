@@ -105,6 +105,7 @@ void default_opts(lpdec::Opts &o)
     o.tau_act = 1e-4;
     o.tau_int = 1e-4;
     o.eps = 1e-8;
+    o.eps_stall = 1e-7;
     o.sigma = 0.1;
     o.eta = 0.9995;
     o.pcg_tol = 1e-6;
@@ -227,6 +228,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
         return LPDEC_OK;
     case LPDEC_OPT_PRECOND: if (v != 0 && v != 1) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
+    case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;
     default: return fail(ctx, LPDEC_EINVAL, "unknown option key %d", key);
     }
     return fail(ctx, LPDEC_EINVAL, "bad value %g for option %d", v, key);
@@ -254,6 +256,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_BLOCK: *v = ctx->block; break;
     case LPDEC_OPT_PRECOND: *v = o.precond; break;
     case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
+    case LPDEC_OPT_IPM_STALL: *v = o.eps_stall; break;
     default: return LPDEC_EINVAL;
     }
     return LPDEC_OK;
@@ -272,7 +275,7 @@ extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, 
     int dcmax = 0;
     for (int j = 0; j < m; ++j) {
         const int d = rowptr[j + 1] - rowptr[j];
-        if (d < 1 || d > 32) return fail(ctx, LPDEC_EINVAL, "row %d has degree %d (need 1..32)", j, d);
+        if (d < 1 || d > 15) return fail(ctx, LPDEC_EINVAL, "row %d has degree %d (need 1..15)", j, d);
         dcmax = std::max(dcmax, d);
         for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) {
             if (col[e] < 0 || col[e] >= n) return fail(ctx, LPDEC_EINVAL, "row %d: column %d out of range", j, col[e]);
@@ -290,6 +293,11 @@ extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, 
     for (int e = 0; e < E; ++e) colptr[col[e] + 1]++;
     for (int i = 0; i < n; ++i) colptr[i + 1] += colptr[i];
     for (int i = 0; i < n; ++i) c->dvmax = std::max(c->dvmax, colptr[i + 1] - colptr[i]);
+    if (c->dvmax > 16) {
+        const int dv = c->dvmax;
+        delete c;
+        return fail(ctx, LPDEC_EINVAL, "a column has degree %d (need <= 16)", dv);
+    }
     std::vector<int> fill(colptr.begin(), colptr.end() - 1);
     for (int j = 0; j < m; ++j)
         for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) vlist[fill[col[e]]++] = (j << 5) | (e - rowptr[j]);
@@ -348,7 +356,7 @@ extern "C" lpdec_status lpdec_decode_batch(lpdec_ctx *ctx, const lpdec_code *cod
     lpdec_status st = check_common(ctx, code, nframes);
     if (st) return st;
     return decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev,
-                             stats_dev, u_dev, nullptr, 0, precision_for(ctx, 0), ctx->ws, (hipStream_t)stream);
+                             stats_dev, u_dev, nullptr, 0, precision_for(ctx, 1), ctx->ws, (hipStream_t)stream);
 }
 
 extern "C" lpdec_status lpdec_decode_batch_trace(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
@@ -360,7 +368,7 @@ extern "C" lpdec_status lpdec_decode_batch_trace(lpdec_ctx *ctx, const lpdec_cod
     if (st) return st;
     if (!trace_dev || trace_cap <= 0) return fail(ctx, LPDEC_EINVAL, "trace buffer required");
     st = decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev, stats_dev,
-                           u_dev, trace_dev, trace_cap, precision_for(ctx, 0), ctx->ws, nullptr);
+                           u_dev, trace_dev, trace_cap, precision_for(ctx, 1), ctx->ws, nullptr);
     if (st) return st;
     hipError_t e = hipDeviceSynchronize();
     return e == hipSuccess ? LPDEC_OK : hipfail(ctx, e, "decode");
@@ -554,7 +562,7 @@ size_t frame_footprint(const lpdec_code *c, int pt64)
 void server_loop(lpdec_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
-    const int pt64 = precision_for(s->ctx, 0);
+    const int pt64 = precision_for(s->ctx, 1);
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         // retire finished waves
@@ -696,7 +704,7 @@ extern "C" lpdec_status lpdec_server_submit(lpdec_server *s, const lpdec_code *c
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return LPDEC_EINVAL;
-        if (frame_footprint(code, precision_for(s->ctx, 0)) > s->budget) return LPDEC_ENOMEM;
+        if (frame_footprint(code, precision_for(s->ctx, 1)) > s->budget) return LPDEC_ENOMEM;
         r.ticket = s->next_ticket++;
         *ticket = r.ticket;
         s->pending[r.ticket] = 1;

@@ -16,7 +16,7 @@ struct Opts {
     int ref_max;
     int precond;     // 1: triangular preconditioner, 0: M = I
     double tau_viol, tau_act, tau_int;
-    double eps, sigma, eta;
+    double eps, eps_stall, sigma, eta;
     double pcg_tol, ref_tol, xi_tol;
 };
 
@@ -34,21 +34,26 @@ struct CodeView {
 // by the triangular-set search; they live in LDS when they fit (else in the frame's global
 // workspace). "cold" arrays hold the FP64 interior-point state in the global workspace.
 // Index lists are uint16 (bit 15 = negative coefficient, bit 14 = row reference, bits
-// 0..13 = index), which bounds n + m by 16383.
+// 0..13 = index), which bounds n + m by 16383. Row-type lists (rlist, bins) use slots of rw
+// entries (a multiple of 8: one 16-byte load per 8), column-type lists (clist, fins) slots
+// of cw entries (a multiple of 4: one 8-byte load per 4), padded with the end marker.
 struct Plan {
+    int rw, cw;                                // slot widths (entries)
+    int lanecols, maskwords;                   // columns per lane of Algorithm 7, mask words
     // hot
-    size_t h, r, v, l, s, idm, om, t, d2f;     // PT: [m] x 7, [n+m] x 2
-    size_t rlist, clist, bins, fins;           // u16 [m*dc], [n*dv], [m*(dc+1)], [m*dv]
+    size_t h, r, v, l, idm, om, st, d2f;       // PT: [m] x 6, st [m + (n+m) + 1], d2f [n+m]
+    size_t rlist, clist, bins, fins;           // u16 [m*rw], [n*cw], [m*rw], [m*cw]
     size_t pair, pairrow, lbv, lfv, order;     // i16 [m], [n], [m], [m], [m]
     size_t boff, foff;                         // i32 [m+1]
     size_t deg, sg;                            // u8 / i8 [n]
     size_t vmask;                              // u32 [m]
-    size_t lbest, ldirty;                      // u64 [64], u32 [64]
+    size_t rank, lcol, lmask;                  // u8 [n+m], u16 [64*lanecols], u32 [64*maskwords]
     size_t hot_bytes;
     // cold, FP64 unless noted
     size_t x, z, dx, dz, rc, tq, d2;           // [n+m]
     size_t y, dy, rb, w, b, rho, f64;          // [m]
     size_t c64;                                // 8 x [m]: FP64 PCG vectors (escalation), dy copy
+    size_t st64;                               // [m + (n+m) + 1]: s | t of the escalated PCG
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
     size_t cold_bytes;
@@ -56,30 +61,43 @@ struct Plan {
 
 __host__ __device__ inline size_t lp_align(size_t v) { return (v + 15) & ~(size_t)15; }
 
+__host__ __device__ inline int lp_pow2_at_least(int v, int lo)
+{
+    int w = lo;
+    while (w < v) w <<= 1;
+    return w;
+}
+
 __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_size)
 {
     Plan p;
+    // a row slot holds a header and up to dc entries (row lists: dc columns), a column slot
+    // a header and up to dv - 1 entries (column lists: dv rows)
+    p.rw = lp_pow2_at_least(dc + 1, 8);
+    p.cw = lp_pow2_at_least(dv, 4);
+    p.lanecols = (n + m + 63) / 64;
+    p.maskwords = (p.lanecols + 31) / 32;
     size_t o = 0;
     const size_t M = (size_t)m, N = (size_t)n, Q = (size_t)n + m, P = (size_t)pt_size;
-    const size_t DC = (size_t)dc, DV = (size_t)dv;
+    const size_t DC = (size_t)p.rw, DV = (size_t)p.cw;
     p.h = o; o = lp_align(o + P * M);
     p.r = o; o = lp_align(o + P * M);
     p.v = o; o = lp_align(o + P * M);
     p.l = o; o = lp_align(o + P * M);
-    p.s = o; o = lp_align(o + P * M);
     p.idm = o; o = lp_align(o + P * M);
     p.om = o; o = lp_align(o + P * M);
-    p.t = o; o = lp_align(o + P * Q);
+    p.st = o; o = lp_align(o + P * (M + Q + 1));
     p.d2f = o; o = lp_align(o + P * Q);
-    p.lbest = o; o = lp_align(o + 8 * 64);
     p.vmask = o; o = lp_align(o + 4 * M);
     p.boff = o; o = lp_align(o + 4 * (M + 1));
     p.foff = o; o = lp_align(o + 4 * (M + 1));
-    p.ldirty = o; o = lp_align(o + 4 * 64);
+    p.lmask = o; o = lp_align(o + 4 * 64 * (size_t)p.maskwords);
     p.rlist = o; o = lp_align(o + 2 * M * DC);
     p.clist = o; o = lp_align(o + 2 * N * DV);
-    p.bins = o; o = lp_align(o + 2 * M * (DC + 1));
+    p.bins = o; o = lp_align(o + 2 * M * DC);
     p.fins = o; o = lp_align(o + 2 * M * DV);
+    p.lcol = o; o = lp_align(o + 2 * 64 * (size_t)p.lanecols);
+    p.rank = o; o = lp_align(o + Q);
     p.pair = o; o = lp_align(o + 2 * M);
     p.pairrow = o; o = lp_align(o + 2 * N);
     p.lbv = o; o = lp_align(o + 2 * M);
@@ -104,6 +122,7 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.rho = o; o = lp_align(o + 8 * M);
     p.f64 = o; o = lp_align(o + 8 * M);
     p.c64 = o; o = o + 8 * lp_align(8 * M);
+    p.st64 = o; o = lp_align(o + 8 * (M + Q + 1));
     p.u = o; o = lp_align(o + 8 * N);
     p.g = o; o = lp_align(o + 8 * N);
     p.active = o; o = lp_align(o + M);

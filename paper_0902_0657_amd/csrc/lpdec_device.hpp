@@ -42,6 +42,118 @@ LPD_INLINE bool e_row(uint16_t e) { return (e & 0x4000u) != 0; }
 template <typename T>
 LPD_INLINE T sgnv(uint16_t e, T v) { return e_neg(e) ? -v : v; }
 
+// Triangular-solve slot entries: (index << 1) | negative. In the PCG the index addresses
+// one vector space, s (rows, [0, m)) followed by t (columns, m + c) and one slot that is
+// always 0 (m + n + m), which also pads every slot; the header entry of a slot holds the
+// row and the sign of its diagonal coefficient.
+LPD_INLINE uint16_t ben(int idx, bool neg) { return (uint16_t)((idx << 1) | (neg ? 1 : 0)); }
+LPD_INLINE int b_idx(uint16_t e) { return e >> 1; }
+LPD_INLINE bool b_neg(uint16_t e) { return (e & 1u) != 0; }
+LPD_INLINE double flip(double v, bool neg)
+{
+    return __hiloint2double(__double2hiint(v) ^ (neg ? (int)0x80000000 : 0), __double2loint(v));
+}
+LPD_INLINE float flip(float v, bool neg) { return __uint_as_float(__float_as_uint(v) ^ (neg ? 0x80000000u : 0u)); }
+// v with sign neg, or +0 when keep is false (integer masks, no branch)
+LPD_INLINE double maskflip(double v, bool neg, bool keep)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long sg = (unsigned long long)neg << 63;
+    return __longlong_as_double((long long)((b ^ sg) & (0ull - (unsigned long long)keep)));
+}
+LPD_INLINE float maskflip(float v, bool neg, bool keep)
+{
+    const uint32_t b = __float_as_uint(v), sg = (uint32_t)neg << 31;
+    return __uint_as_float((b ^ sg) & (0u - (uint32_t)keep));
+}
+
+// Sum over aligned groups of G lanes (4, 8 or 16) with DPP: quad_perm [1,0,3,2] and
+// [2,3,0,1] within quads, then row_half_mirror and row_mirror. Every lane of a group ends
+// with the same sum (each step adds two operands in either order). All lanes must be active.
+template <int CTRL>
+LPD_INLINE double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+LPD_INLINE float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// Makes the compiler materialise v here, so that a load feeding v stays where it is issued
+// (beside the other loads of a step) instead of being sunk into the branch that uses it.
+LPD_INLINE void pin(double v) { asm volatile("" ::"v"(v)); }
+LPD_INLINE void pin(float v) { asm volatile("" ::"v"(v)); }
+
+template <int G, typename T>
+LPD_INLINE T gsum(T v)
+{
+    v = v + dpp_mov<0xB1>(v);
+    v = v + dpp_mov<0x4E>(v);
+    if constexpr (G >= 8) v = v + dpp_mov<0x141>(v);
+    if constexpr (G >= 16) v = v + dpp_mov<0x140>(v);
+    return v;
+}
+
+// A chunk of list entries read with one load: 8 entries (16 bytes) of a row-type slot or 4
+// entries (8 bytes) of a column-type slot. Every entry of a chunk is processed without a
+// data-dependent exit, so the gathers it feeds are issued together.
+struct Ch8 {
+    uint32_t w[4];
+    static constexpr int K = 8;
+};
+struct Ch4 {
+    uint32_t w[2];
+    static constexpr int K = 4;
+};
+LPD_INLINE void ldch(Ch8 &c, const uint16_t *p)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    c.w[0] = v.x; c.w[1] = v.y; c.w[2] = v.z; c.w[3] = v.w;
+}
+LPD_INLINE void ldch(Ch4 &c, const uint16_t *p)
+{
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    c.w[0] = v.x; c.w[1] = v.y;
+}
+template <typename CH>
+LPD_INLINE void endch(CH &c)
+{
+#pragma unroll
+    for (int k = 0; k < CH::K / 2; ++k) c.w[k] = 0xFFFFFFFFu;
+}
+template <typename CH>
+LPD_INLINE uint16_t at(const CH &c, int k) { return (uint16_t)(c.w[k >> 1] >> ((k & 1) << 4)); }
+
+// v with the sign of entry e applied, or +0 when keep is false, computed with integer masks:
+// with no branch for the compiler to sink the load of v into, the loads of consecutive entries
+// are issued back to back and overlap their latencies.
+LPD_INLINE double sgn_keep(double v, uint16_t e, bool keep)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long sg = (unsigned long long)(e & 0x8000u) << 48;
+    const unsigned long long km = 0ull - (unsigned long long)keep;
+    return __longlong_as_double((long long)((b ^ sg) & km));
+}
+LPD_INLINE float sgn_keep(float v, uint16_t e, bool keep)
+{
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t sg = (uint32_t)(e & 0x8000u) << 16;
+    const uint32_t km = 0u - (uint32_t)keep;
+    return __uint_as_float((b ^ sg) & km);
+}
+
+// Signed value of one list entry (0 for the end marker); the load is unconditional (index 0
+// for the marker).
+template <typename T, typename V>
+LPD_INLINE T sgather(uint16_t e, const V *base)
+{
+    const bool ok = e != kEnd;
+    return sgn_keep((T)base[ok ? e_idx(e) : 0], e, ok);
+}
+
 // -------------------------------------------------------------------- wave reductions
 // Inclusive scan inside rows of 16 lanes (row_shr 1, 2, 4, 8), then across rows
 // (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2 and 3); lane 63 ends up with the
@@ -305,30 +417,39 @@ struct Frame {
     uint8_t *deg;
     int8_t *sg;
     uint32_t *vmask;
-    unsigned long long *lbest;
-    uint32_t *ldirty;
+    uint8_t *rank;       // rank of a column among the columns of its lane (Algorithm 7)
+    uint16_t *lcol;      // the columns of each lane by rank: lcol[r * 64 + lane]
+    uint32_t *lmask;     // available columns of each lane by rank: word w at lmask[w * 64 + lane]
+    int RWC, CWC, MW;    // chunks per row slot, per column slot; mask words per lane
     // cold
     double *x, *z, *dx, *dz, *rc, *tq, *d2, *y, *dy, *rb, *w, *b, *rho, *f64, *u, *g;
     double *c64[8];   // FP64 PCG vectors for escalated solves, and a copy of dy
+    double *st64;     // s | t | 0 of the escalated FP64 PCG
     uint8_t *active;
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
+    int Z;                 // index of the zero slot of the PCG vector space (n + 2m)
+    long long ticks_pcg;   // clock ticks spent inside pcg() during the current decode
 
     LPD_INLINE void bind(const Args &a, char *hot, char *cold, Scratch *scr)
     {
-        cd = a.code; o = a.o; m = cd.m; n = cd.n; RW = cd.dcmax; CW = cd.dvmax;
+        cd = a.code; o = a.o; m = cd.m; n = cd.n; RW = a.plan.rw; CW = a.plan.cw;
+        RWC = RW / 8; CWC = CW / 4; MW = a.plan.maskwords;
         tid = threadIdx.x; nt = blockDim.x; sc = scr;
+        ticks_pcg = 0;
         const Plan &P = a.plan;
         h = (PT *)(hot + P.h); r = (PT *)(hot + P.r); v = (PT *)(hot + P.v); l = (PT *)(hot + P.l);
-        s = (PT *)(hot + P.s); idm = (PT *)(hot + P.idm); om = (PT *)(hot + P.om);
-        t = (PT *)(hot + P.t); d2f = (PT *)(hot + P.d2f);
+        s = (PT *)(hot + P.st); idm = (PT *)(hot + P.idm); om = (PT *)(hot + P.om);
+        t = s + m; d2f = (PT *)(hot + P.d2f);
+        Z = n + 2 * m;
+        st64 = (double *)(cold + P.st64);
         rlist = (uint16_t *)(hot + P.rlist); clist = (uint16_t *)(hot + P.clist);
         bins = (uint16_t *)(hot + P.bins); fins = (uint16_t *)(hot + P.fins);
         pair = (int16_t *)(hot + P.pair); pairrow = (int16_t *)(hot + P.pairrow);
         lbv = (int16_t *)(hot + P.lbv); lfv = (int16_t *)(hot + P.lfv); order = (int16_t *)(hot + P.order);
         boff = (int *)(hot + P.boff); foff = (int *)(hot + P.foff);
         deg = (uint8_t *)(hot + P.deg); sg = (int8_t *)(hot + P.sg); vmask = (uint32_t *)(hot + P.vmask);
-        lbest = (unsigned long long *)(hot + P.lbest); ldirty = (uint32_t *)(hot + P.ldirty);
+        rank = (uint8_t *)(hot + P.rank); lcol = (uint16_t *)(hot + P.lcol); lmask = (uint32_t *)(hot + P.lmask);
         x = (double *)(cold + P.x); z = (double *)(cold + P.z); dx = (double *)(cold + P.dx);
         dz = (double *)(cold + P.dz); rc = (double *)(cold + P.rc); tq = (double *)(cold + P.tq);
         d2 = (double *)(cold + P.d2); y = (double *)(cold + P.y); dy = (double *)(cold + P.dy);
@@ -383,12 +504,12 @@ struct Frame {
     template <typename T, typename V>
     LPD_INLINE T row_dot(int j, const V *xq) const
     {
-        const uint16_t *L = rlist + (size_t)j * RW;
         T acc = (T)xq[n + j];
-        for (int k = 0; k < RW; ++k) {
-            const uint16_t e = L[k];
-            if (e == kEnd) break;
-            acc += sgnv(e, (T)xq[e_idx(e)]);
+        for (int ch = 0; ch < RWC; ++ch) {
+            Ch8 E;
+            ldch(E, rlist + (size_t)j * RW + 8 * ch);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += sgather<T>(at(E, k), xq);
         }
         return acc;
     }
@@ -396,12 +517,12 @@ struct Frame {
     template <typename T, typename V>
     LPD_INLINE T col_dot(int i, const V *yy) const
     {
-        const uint16_t *L = clist + (size_t)i * CW;
         T acc = 0;
-        for (int k = 0; k < CW; ++k) {
-            const uint16_t e = L[k];
-            if (e == kEnd) break;
-            acc += sgnv(e, (T)yy[e_idx(e)]);
+        for (int ch = 0; ch < CWC; ++ch) {
+            Ch4 E;
+            ldch(E, clist + (size_t)i * CW + 4 * ch);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += sgather<T>(at(E, k), yy);
         }
         return acc;
     }
@@ -432,38 +553,38 @@ struct Frame {
 
     // ------------------------------------------------------------ Algorithm 7 + levels
     LPD_INLINE float wt(const float *wk, int c) const { return wk ? wk[c] : (float)d2f[c]; }
-
-    // preferred available column among those owned by one lane (c = lane + 64 k)
-    LPD_INLINE unsigned long long lane_best(const float *wk, int lane) const
+    LPD_INLINE bool present(int c) const { return c < n || cut(c - n); }
+    LPD_INLINE unsigned long long colkey(const float *wk, int c) const { return mts_key(wt(wk, c), c); }
+    LPD_INLINE void mask_set(int c, bool on)
     {
-        unsigned long long best = 0ull;
-        for (int c = lane; c < n + m; c += 64) {
-            bool av;
-            if (c < n) av = pairrow[c] < 0 && deg[c] == 1;
-            else av = cut(c - n) && pair[c - n] < 0;
-            if (av) {
-                const unsigned long long k = mts_key(wt(wk, c), c);
-                best = k > best ? k : best;
-            }
-        }
-        return best;
+        const int r = rank[c];
+        uint32_t *wp = &lmask[(r >> 5) * 64 + (c & 63)];
+        if (on) atomicOr(wp, 1u << (r & 31));
+        else atomicAnd(wp, ~(1u << (r & 31)));
     }
 
     // Column-wise greedy search for the triangular set (Algorithm 7), exactly as stated:
     // p times, take the degree-1 column with the largest key (weight, then lowest index)
-    // and eliminate the only row it still has. Wave 0 runs it: every lane keeps the best
-    // available column of the columns it owns (lbest), the wave takes the maximum, and the
-    // lanes of the eliminated row update the residual degrees of its columns. A lane whose
-    // best column was taken or lost its last row rescans its columns.
+    // and eliminate the only row it still has.
+    //   Lane l of wave 0 owns the columns c = l + 64 r. Before the search the columns of each
+    // lane are ranked by key (lcol lists them by rank) and a bit mask per lane marks the
+    // available ones (degree 1, not taken; a slack column while its row is live). A lane's
+    // best column is its lowest set bit, the chosen column the wave maximum of the lanes'
+    // keys. Eliminating a row clears the bits of the chosen column and of the row's slack,
+    // and the row's other columns lose one degree: 2 -> 1 sets their bit, 1 -> 0 clears it.
     // Fills pair (column of each row), pairrow (row of each chosen standard column), order
     // (rows in elimination order), lfv (forward-substitution level) and lbv
     // (back-substitution level). Returns p.
     LPD_INLINE int mts(const float *wk)
     {
         for (int i = tid; i < n; i += nt) {
-            const uint16_t *L = clist + (size_t)i * CW;
             int dg = 0;
-            for (int k = 0; k < CW && L[k] != kEnd; ++k) ++dg;
+            for (int ch = 0; ch < CWC; ++ch) {
+                Ch4 E;
+                ldch(E, clist + (size_t)i * CW + 4 * ch);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dg += at(E, k) != kEnd;
+            }
             deg[i] = (uint8_t)dg;
             pairrow[i] = -1;
         }
@@ -472,77 +593,123 @@ struct Frame {
             pair[j] = -1; lfv[j] = -1; lbv[j] = -1;
             pl += cut(j);
         }
+        for (int k = tid; k < 64 * MW; k += nt) lmask[k] = 0u;
         pl = block_sum1(pl, sc);
         p = pl;
+        // rank of each present column among the present columns of its lane
+        for (int c = tid; c < n + m; c += nt) {
+            if (!present(c)) continue;
+            const unsigned long long kc = colkey(wk, c);
+            int r = 0;
+            for (int c2 = c & 63; c2 < n + m; c2 += 64) {
+                const unsigned long long k2 = present(c2) ? colkey(wk, c2) : 0ull;
+                r += k2 > kc;
+            }
+            rank[c] = (uint8_t)r;
+            lcol[r * 64 + (c & 63)] = (uint16_t)c;
+        }
+        __syncthreads();
+        for (int c = tid; c < n + m; c += nt)
+            if (present(c) && (c >= n || deg[c] == 1)) mask_set(c, true);
+        __syncthreads();
+        int done = 0;   // rows eliminated (wave 0)
         if (tid < 64) {
             const int lane = tid;
-            lbest[lane] = lane_best(wk, lane);
-            ldirty[lane] = 0;
+            const int le = lane < RW ? lane : RW - 1;   // entry of the eliminated row this lane reads
             for (int step = 0; step < pl; ++step) {
                 __builtin_amdgcn_wave_barrier();
-                unsigned long long mine = lbest[lane];
-                if (ldirty[lane]) {
-                    mine = lane_best(wk, lane);
-                    lbest[lane] = mine;
-                    ldirty[lane] = 0;
+                int r = -1;
+                for (int wd = 0; wd < MW && r < 0; ++wd) {
+                    const uint32_t bits = lmask[wd * 64 + lane];
+                    if (bits) r = wd * 32 + __builtin_ctz(bits);
                 }
+                const int cl = r >= 0 ? (int)lcol[r * 64 + lane] : 0;
+                const unsigned long long kl = colkey(wk, cl);
+                const unsigned long long mine = r >= 0 ? kl : 0ull;
                 const unsigned long long K = wave_max_u64(mine);
                 if (K == 0ull) break;   // no degree-1 column: cannot happen while rows remain
                 const int c = mts_key_col(K);
                 // the row of c: its only live row; the other rows give the forward level
-                int row, L = 0;
-                if (c >= n) {
-                    row = c - n;
-                } else {
+                int row = c - n, L = 0;
+                if (c < n) {
                     row = -1;
-                    const uint16_t *CL = clist + (size_t)c * CW;
-                    for (int k = 0; k < CW; ++k) {
-                        const uint16_t e = CL[k];
-                        if (e == kEnd) break;
-                        const int j = e_idx(e);
-                        if (pair[j] < 0) row = j;
-                        else L = max(L, (int)lfv[j] + 1);
+                    for (int ch = 0; ch < CWC; ++ch) {
+                        Ch4 E;
+                        ldch(E, clist + (size_t)c * CW + 4 * ch);
+                        int pj[4], lj[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint16_t e = at(E, k);
+                            const int j = e != kEnd ? e_idx(e) : 0;
+                            pj[k] = pair[j];
+                            lj[k] = lfv[j];
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint16_t e = at(E, k);
+                            const bool ok = e != kEnd;
+                            row = ok && pj[k] < 0 ? e_idx(e) : row;
+                            L = ok && pj[k] >= 0 ? max(L, lj[k] + 1) : L;
+                        }
                     }
                     if (row < 0) break;   // a degree-1 column always has its live row
                 }
+                // everything the updates read, loaded together
+                const uint16_t e = rlist[(size_t)row * RW + le];
+                const bool ok = lane < RW && e != kEnd;
+                const int i = ok ? e_idx(e) : 0;
+                const int pri = pairrow[i], dgi = deg[i] - 1, rki = rank[i];
+                const int rkc = rank[c], rks = rank[n + row];
                 __builtin_amdgcn_wave_barrier();
                 if (lane == 0) {
                     pair[row] = (int16_t)c;
                     lfv[row] = (int16_t)L;
                     order[step] = (int16_t)row;
                     if (c < n) pairrow[c] = (int16_t)row;
-                    ldirty[c & 63] = 1;
-                    ldirty[(n + row) & 63] = 1;
+                    atomicAnd(&lmask[(rkc >> 5) * 64 + (c & 63)], ~(1u << (rkc & 31)));
+                    if (c != n + row) atomicAnd(&lmask[(rks >> 5) * 64 + ((n + row) & 63)], ~(1u << (rks & 31)));
                 }
-                __builtin_amdgcn_wave_barrier();
                 // eliminate the row: its waiting columns lose one degree
-                if (lane < RW) {
-                    const uint16_t e = rlist[(size_t)row * RW + lane];
-                    if (e != kEnd) {
-                        const int i = e_idx(e);
-                        if (i != c && pairrow[i] < 0) {
-                            const int dgi = deg[i] - 1;
-                            deg[i] = (uint8_t)dgi;
-                            if (dgi == 1) atomicMax(&lbest[i & 63], mts_key(wt(wk, i), i));
-                            else if (dgi == 0) ldirty[i & 63] = 1;
-                        }
-                    }
+                if (ok && i != c && pri < 0) {
+                    deg[i] = (uint8_t)dgi;
+                    uint32_t *wp = &lmask[(rki >> 5) * 64 + (i & 63)];
+                    if (dgi == 1) atomicOr(wp, 1u << (rki & 31));
+                    else if (dgi == 0) atomicAnd(wp, ~(1u << (rki & 31)));
                 }
+                done = step + 1;
             }
-            __builtin_amdgcn_wave_barrier();
-            // back-substitution levels, rows in reverse elimination order: a row depends on
-            // the rows of the other chosen columns in it, all eliminated later
-            for (int step = pl - 1; step >= 0; --step) {
-                const int row = order[step], c = pair[row];
-                int L = 0;
-                if (lane < RW) {
-                    const uint16_t e = rlist[(size_t)row * RW + lane];
-                    if (e != kEnd) {
-                        const int i = e_idx(e);
-                        if (i != c && pairrow[i] >= 0) L = lbv[pairrow[i]] + 1;
-                    }
+        }
+        __syncthreads();
+        // back-substitution levels: a row depends on the rows of the other chosen columns in
+        // it, all eliminated later. The dependencies are listed in parallel (into bins, which
+        // the level build rewrites afterwards), then wave 0 walks the rows in reverse
+        // elimination order with the next row's list prefetched.
+        uint16_t *dep = bins;
+        for (int j = tid; j < m; j += nt) {
+            if (!cut(j)) continue;
+            const int c = pair[j];
+            for (int k = 0; k < RW; ++k) {
+                const uint16_t e = rlist[(size_t)j * RW + k];
+                const int i = e != kEnd ? e_idx(e) : 0;
+                const int pr = pairrow[i];
+                dep[(size_t)j * RW + k] = (e != kEnd && i != c && pr >= 0) ? (uint16_t)pr : kEnd;
+            }
+        }
+        __syncthreads();
+        if (tid < 64 && done > 0) {
+            const int lane = tid;
+            const int le = lane < RW ? lane : RW - 1;
+            int rown = order[done - 1];
+            uint16_t dn = dep[(size_t)rown * RW + le];
+            for (int step = done - 1; step >= 0; --step) {
+                const int row = rown;
+                const uint16_t dd = lane < RW ? dn : kEnd;
+                if (step > 0) {
+                    rown = order[step - 1];
+                    dn = dep[(size_t)rown * RW + le];
                 }
-                L = (int)wave_max_u32((uint32_t)L);
+                const int lv = lbv[dd != kEnd ? dd : 0];
+                const int L = (int)wave_max_u32(dd != kEnd ? (uint32_t)(lv + 1) : 0u);
                 if (lane == 0) lbv[row] = (int16_t)L;
                 __builtin_amdgcn_wave_barrier();
             }
@@ -567,12 +734,12 @@ struct Frame {
     }
 
     // Rows grouped by level, each with its instruction list. Back-substitution level L holds
-    // slots [L ? boff[L-1] : 0, boff[L]) of bins (RW+1 entries per slot), forward level L
-    // slots [L ? foff[L-1] : 0, foff[L]) of fins (CW entries per slot). Slot header: the row
-    // and the sign of its diagonal entry. Back entries: the other M-columns of the row as
-    // references to their rows (coefficient negated), the columns outside M (the slack
-    // included) as column references. Forward entries: the other rows of the paired column
-    // (coefficient negated).
+    // slots [L ? boff[L-1] : 0, boff[L]) of bins (RW entries per slot), forward level L
+    // slots [L ? foff[L-1] : 0, foff[L]) of fins (CW entries per slot), entries encoded by
+    // ben(). Slot header: the row and the sign of its diagonal entry. Back entries: the other
+    // M-columns of the row as references to their rows (index < m, coefficient negated), the
+    // columns outside M (the slack included) as column references (index m + column).
+    // Forward entries: the other rows of the paired column (coefficient negated).
     LPD_INLINE void build_levels()
     {
         int mb = -1, mf = -1;
@@ -594,7 +761,7 @@ struct Frame {
             const int c = pair[j];
             // back-substitution slot
             {
-                uint16_t *B = bins + (size_t)atomicAdd(&boff[lbv[j]], 1) * (RW + 1);
+                uint16_t *B = bins + (size_t)atomicAdd(&boff[lbv[j]], 1) * RW;
                 const uint16_t *L = rlist + (size_t)j * RW;
                 bool dneg = false;
                 int q = 1;
@@ -603,12 +770,12 @@ struct Frame {
                     if (e == kEnd) break;
                     const int i = e_idx(e);
                     if (i == c) { dneg = e_neg(e); continue; }
-                    if (pairrow[i] >= 0) B[q++] = enc(pairrow[i], !e_neg(e), true);
-                    else B[q++] = enc(i, e_neg(e), false);
+                    if (pairrow[i] >= 0) B[q++] = ben(pairrow[i], !e_neg(e));
+                    else B[q++] = ben(m + i, e_neg(e));
                 }
-                if (c != n + j) B[q++] = enc(n + j, false, false);
-                for (; q <= RW; ++q) B[q] = kEnd;
-                B[0] = enc(j, dneg, false);
+                if (c != n + j) B[q++] = ben(m + n + j, false);
+                for (; q < RW; ++q) B[q] = ben(Z, false);
+                B[0] = ben(j, dneg);
             }
             // forward-substitution slot
             {
@@ -622,11 +789,11 @@ struct Frame {
                         if (e == kEnd) break;
                         const int jj = e_idx(e);
                         if (jj == j) { dneg = e_neg(e); continue; }
-                        F[q++] = enc(jj, !e_neg(e), true);
+                        F[q++] = ben(jj, !e_neg(e));
                     }
                 }
-                for (; q < CW; ++q) F[q] = kEnd;
-                F[0] = enc(j, dneg, false);
+                for (; q < CW; ++q) F[q] = ben(Z, false);
+                F[0] = ben(j, dneg);
             }
         }
         __syncthreads();
@@ -636,48 +803,93 @@ struct Frame {
     // The preconditioning set M pairs every LP row j with one column pair[j]; A_M (rows by
     // paired columns) is triangular after permutation with entries +-1 (Sec. V). Vectors over
     // M's columns are stored at the row each column is paired with.
-    // Back-substitution out = A_M^-1 u (levels ascending).
-    template <typename T, typename UF>
-    LPD_INLINE void back_sub(T *out, UF u_of_row)
+    //
+    // Level-by-level sweep over the slots of one triangular solve, one lane per slot entry:
+    // groups of G lanes (G = slot width) take the slots of a level. Every lane computes the
+    // value of its entry (gather; the header lane q = 0 contributes 0) and whatever the row's
+    // finish needs (pre), the group sums the values with DPP, and the header lane finishes
+    // the row. Levels are separated by a barrier; level bounds are read two levels ahead and
+    // each lane's entry of the next level one level ahead.
+    template <int G, typename T, typename GF, typename PF, typename FF>
+    LPD_INLINE void gsweep(const uint16_t *slots, const int *off, int nlev, GF gather, PF pre, FF finish)
     {
-        for (int L = 0; L < nlb; ++L) {
-            const int k1 = boff[L];
-            for (int k = (L ? boff[L - 1] : 0) + tid; k < k1; k += nt) {
-                const uint16_t *B = bins + (size_t)k * (RW + 1);
-                const uint16_t hd = B[0];
-                const int j = e_idx(hd);
-                T acc = u_of_row(j);
-                for (int q = 1; q <= RW; ++q) {
-                    const uint16_t e = B[q];
-                    if (e == kEnd) break;
-                    if (e_row(e)) acc += sgnv(e, out[e_idx(e)]);
-                }
-                out[j] = e_neg(hd) ? -acc : acc;
+        if (nlev <= 0) return;
+        const int g = tid / G, q = tid - g * G, ng = nt / G;
+        const uint16_t zero = ben(Z, false);
+        auto step = [&](bool valid, uint16_t e) {
+            const T v = gather(valid, e, q);
+            const auto pc = pre(valid && q == 0, e);
+            const T sum = gsum<G>(v);
+            finish(valid && q == 0, e, pc, sum);
+        };
+        int k0 = 0, k1 = off[0], k2 = nlev > 1 ? off[1] : k1;
+        uint16_t cur = g < k1 ? slots[g * G + q] : zero;
+        for (int L = 0; L < nlev; ++L) {
+            const int k3 = L + 2 < nlev ? off[L + 2] : k2;
+            const uint16_t nxt = k1 + g < k2 ? slots[(k1 + g) * G + q] : zero;
+            step(k0 + g < k1, cur);
+            for (int kb = k0 + ng; kb < k1; kb += ng) {
+                const int k = kb + g;
+                step(k < k1, k < k1 ? slots[k * G + q] : zero);
             }
             __syncthreads();
+            k0 = k1; k1 = k2; k2 = k3;
+            cur = nxt;
         }
     }
 
-    // Forward substitution out = A_M^-T e (out in row space; levels ascending).
+    // Back-substitution out = A_M^-1 u (levels ascending); out has m entries, only the row
+    // references of the slots are used.
+    template <int G, typename T, typename UF>
+    LPD_INLINE void back_sub_g(T *out, UF u_of_row)
+    {
+        gsweep<G, T>(
+            bins, boff, nlb,
+            [&](bool valid, uint16_t e, int q) {
+                const int bi = b_idx(e);
+                const bool ok = valid && q != 0 && bi < m;
+                return maskflip((T)out[ok ? bi : 0], b_neg(e), ok);
+            },
+            [&](bool head, uint16_t e) { return (T)u_of_row(head ? b_idx(e) : 0); },
+            [&](bool head, uint16_t e, T u0, T sum) {
+                if (head) {
+                    const T acc = u0 + sum;
+                    out[b_idx(e)] = b_neg(e) ? -acc : acc;
+                }
+            });
+    }
+    template <typename T, typename UF>
+    LPD_INLINE void back_sub(T *out, UF u_of_row)
+    {
+        if (RW == 8) back_sub_g<8>(out, u_of_row);
+        else back_sub_g<16>(out, u_of_row);
+    }
+
+    // Forward substitution out = A_M^-T e (out in row space, m entries; levels ascending).
+    template <int G, typename T, typename EF>
+    LPD_INLINE void fwd_sub_g(T *out, EF e_of_row)
+    {
+        gsweep<G, T>(
+            fins, foff, nlf,
+            [&](bool valid, uint16_t e, int q) {
+                const int bi = b_idx(e);
+                const bool ok = valid && q != 0 && bi < m;
+                return maskflip((T)out[ok ? bi : 0], b_neg(e), ok);
+            },
+            [&](bool head, uint16_t e) { return (T)e_of_row(head ? b_idx(e) : 0); },
+            [&](bool head, uint16_t e, T e0, T sum) {
+                if (head) {
+                    const T acc = e0 + sum;
+                    out[b_idx(e)] = b_neg(e) ? -acc : acc;
+                }
+            });
+    }
     template <typename T, typename EF>
     LPD_INLINE void fwd_sub(T *out, EF e_of_row)
     {
-        for (int L = 0; L < nlf; ++L) {
-            const int k1 = foff[L];
-            for (int k = (L ? foff[L - 1] : 0) + tid; k < k1; k += nt) {
-                const uint16_t *F = fins + (size_t)k * CW;
-                const uint16_t hd = F[0];
-                const int j = e_idx(hd);
-                T acc = e_of_row(j);
-                for (int q = 1; q < CW; ++q) {
-                    const uint16_t e = F[q];
-                    if (e == kEnd) break;
-                    acc += sgnv(e, out[e_idx(e)]);
-                }
-                out[j] = e_neg(hd) ? -acc : acc;
-            }
-            __syncthreads();
-        }
+        if (CW == 4) fwd_sub_g<4>(out, e_of_row);
+        else if (CW == 8) fwd_sub_g<8>(out, e_of_row);
+        else fwd_sub_g<16>(out, e_of_row);
     }
 
     LPD_INLINE bool in_M(int c) const { return c < n ? pairrow[c] >= 0 : pair[c - n] == c; }
@@ -706,47 +918,79 @@ struct Frame {
     template <typename T>
     LPD_INLINE int pcg(const CG<T> &V, T tol, T xi_stop, int maxit)
     {
+        if (RW == 8) {
+            if (CW == 4) return pcg_g<T, 8, 4>(V, tol, xi_stop, maxit);
+            if (CW == 8) return pcg_g<T, 8, 8>(V, tol, xi_stop, maxit);
+            return pcg_g<T, 8, 16>(V, tol, xi_stop, maxit);
+        }
+        if (CW == 4) return pcg_g<T, 16, 4>(V, tol, xi_stop, maxit);
+        if (CW == 8) return pcg_g<T, 16, 8>(V, tol, xi_stop, maxit);
+        return pcg_g<T, 16, 16>(V, tol, xi_stop, maxit);
+    }
+
+    // V.s and V.t are one vector space (t = s + m) whose element Z is 0; the slot entries
+    // index it directly, so the sweeps need no masks.
+    template <typename T, int GB, int GF>
+    LPD_INLINE int pcg_g(const CG<T> &V, T tol, T xi_stop, int maxit)
+    {
         T rr = 0;
+        if (tid == 0) V.s[Z] = (T)0;
         for (int j = tid; j < m; j += nt) { V.h[j] = V.r[j]; rr += V.r[j] * V.r[j]; }
         rr = block_sum1(rr, sc);
         if (!(rr > (T)0)) return 0;
         const T stop = tol * tol * rr;
+        T *const S = V.s;
         int it = 0;
         while (it < maxit) {
             // s = A_M^-T (D_M^-1 h)
-            fwd_sub<T>(V.s, [&](int j) { return V.h[j] * V.idm[j]; });
+            gsweep<GF, T>(
+                fins, foff, nlf,
+                [&](bool valid, uint16_t e, int q) { return flip(S[valid && q ? b_idx(e) : Z], b_neg(e)); },
+                [&](bool head, uint16_t e) {
+                    const int j = head ? b_idx(e) : 0;
+                    const T e0 = V.h[j] * V.idm[j];
+                    pin(e0);
+                    return e0;
+                },
+                [&](bool head, uint16_t e, T e0, T sum) {
+                    if (head) {
+                        const T acc = e0 + sum;
+                        S[b_idx(e)] = b_neg(e) ? -acc : acc;
+                    }
+                });
             // t = D_N^2 A_N^T s on the columns outside M
             for (int c = tid; c < n + m; c += nt) {
                 if (c < n) {
-                    if (pairrow[c] < 0) V.t[c] = V.dsq[c] * col_dot<T>(c, V.s);
+                    if (pairrow[c] < 0) V.t[c] = V.dsq[c] * col_dot<T>(c, S);
                 } else {
                     const int j = c - n;
-                    if (cut(j) && pair[j] != c) V.t[c] = V.dsq[c] * V.s[j];
+                    if (cut(j) && pair[j] != c) V.t[c] = V.dsq[c] * S[j];
                 }
             }
             __syncthreads();
             // f = A_M^-1 (A_N t) over s; l = h + D_M^-1 f
             T hl = 0;
-            for (int L = 0; L < nlb; ++L) {
-                const int k1 = boff[L];
-                for (int k = (L ? boff[L - 1] : 0) + tid; k < k1; k += nt) {
-                    const uint16_t *B = bins + (size_t)k * (RW + 1);
-                    const uint16_t hd = B[0];
-                    const int j = e_idx(hd);
-                    T acc = 0;
-                    for (int q = 1; q <= RW; ++q) {
-                        const uint16_t e = B[q];
-                        if (e == kEnd) break;
-                        acc += sgnv(e, e_row(e) ? V.s[e_idx(e)] : V.t[e_idx(e)]);
+            struct HI { T h, i; };
+            gsweep<GB, T>(
+                bins, boff, nlb,
+                [&](bool valid, uint16_t e, int q) { return flip(S[valid && q ? b_idx(e) : Z], b_neg(e)); },
+                [&](bool head, uint16_t e) {
+                    const int j = head ? b_idx(e) : 0;
+                    const HI hi{V.h[j], V.idm[j]};
+                    pin(hi.h);
+                    pin(hi.i);
+                    return hi;
+                },
+                [&](bool head, uint16_t e, HI hi, T sum) {
+                    if (head) {
+                        const int j = b_idx(e);
+                        const T fj = b_neg(e) ? -sum : sum;
+                        S[j] = fj;
+                        const T lj = hi.h + fj * hi.i;
+                        V.l[j] = lj;
+                        hl += hi.h * lj;
                     }
-                    const T fj = e_neg(hd) ? -acc : acc;
-                    V.s[j] = fj;
-                    const T lj = V.h[j] + fj * V.idm[j];
-                    V.l[j] = lj;
-                    hl += V.h[j] * lj;
-                }
-                __syncthreads();
-            }
+                });
             hl = block_sum1(hl, sc);
             if (!(hl > (T)0)) break;
             const T alpha = rr / hl;
@@ -788,7 +1032,9 @@ struct Frame {
             }
         }
         __syncthreads();
+        const long long t0 = wall_clock64();
         const int its = pcg<T>(V, (T)tol, (T)xi_stop, o.pcg_maxit);
+        ticks_pcg += wall_clock64() - t0;
         fwd_sub<double>(f64, [&](int j) { return (double)V.v[j] / sqrt(d2[pair[j]]); });
         for (int j = tid; j < m; j += nt)
             if (cut(j)) dy[j] += f64[j];
@@ -815,12 +1061,12 @@ struct Frame {
         double nr2 = 0.0;
         for (int j = tid; j < m; j += nt) {
             if (!cut(j)) continue;
-            const uint16_t *L = rlist + (size_t)j * RW;
             double acc = d2[n + j] * dy[j];
-            for (int k = 0; k < RW; ++k) {
-                const uint16_t e = L[k];
-                if (e == kEnd) break;
-                acc += sgnv(e, tq[e_idx(e)]);
+            for (int ch = 0; ch < RWC; ++ch) {
+                Ch8 E;
+                ldch(E, rlist + (size_t)j * RW + 8 * ch);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc += sgather<double>(at(E, k), tq);
             }
             const double rj = w[j] - acc;
             rho[j] = rj;
@@ -860,7 +1106,7 @@ struct Frame {
         const bool use_xi = mu > 0.0;
         const double xi_goal = o.xi_tol * mu;
         CG<PT> V1 = {r, v, h, l, s, t, idm, om, d2f};
-        CG<double> V2 = {c64[0], c64[1], c64[2], c64[3], c64[4], tq, c64[5], c64[6], d2};
+        CG<double> V2 = {c64[0], c64[1], c64[2], c64[3], st64, st64 + m, c64[5], c64[6], d2};
         const double tol1 = sizeof(PT) == 8 ? (o.ref_tol < o.pcg_tol ? o.ref_tol : o.pcg_tol) : o.pcg_tol;
         const double tol2 = o.ref_tol < o.pcg_tol ? o.ref_tol : o.pcg_tol;
         const double xs = use_xi ? xi_goal : 0.0;
@@ -910,7 +1156,9 @@ struct Frame {
     // (A D^2 A^T) dy = r_b + A D^2 r_c - A Z^-1 r_e, dx = D^2 A^T dy - D^2 r_c + Z^-1 r_e,
     // dz = X^-1 (r_e - Z dx); separate primal and dual step lengths (fraction eta of the
     // distance to the boundary, at most 1). Starts at x = e, y = 0, z = e; stops when
-    // x^T z / (1 + |c^T x|), ||r_b|| / (1 + ||b||) and ||r_c|| / (1 + ||c||) are all < eps.
+    // x^T z / (1 + |c^T x|), ||r_b|| / (1 + ||b||) and ||r_c|| / (1 + ||c||) are all < eps,
+    // or when the largest of them is below eps_stall and has not at least halved over the
+    // last two iterations (the double-precision floor of a degenerate LP).
     // The LP's row and column lists must be built. Returns 0 or a negative LPDEC_FLAG_*.
     LPD_INLINE int ipm(lpdec_stats &st, int &iters)
     {
@@ -947,6 +1195,7 @@ struct Frame {
         const double nb = sqrt(a0[0]), nc = sqrt(a0[1]);
         const double q = (double)(n + p);
         int status = LPDEC_FLAG_IPM_CAP, it;
+        double phi1 = INFINITY, phi2 = INFINITY;   // error measure one and two iterations ago
         for (it = 0; it < o.ipm_max; ++it) {
             double a[4] = {0.0, 0.0, 0.0, 0.0};   // gap, c^T x, ||r_b||^2, ||r_c||^2
             for (int j = tid; j < m; j += nt) {
@@ -970,11 +1219,14 @@ struct Frame {
                 status = LPDEC_FLAG_NONFINITE;
                 break;
             }
-            if (a[0] / (1.0 + fabs(a[1])) < o.eps && sqrt(a[2]) / (1.0 + nb) < o.eps &&
-                sqrt(a[3]) / (1.0 + nc) < o.eps) {
+            const double phi = fmax(a[0] / (1.0 + fabs(a[1])),
+                                    fmax(sqrt(a[2]) / (1.0 + nb), sqrt(a[3]) / (1.0 + nc)));
+            if (phi < o.eps || (phi < o.eps_stall && phi > 0.5 * phi2)) {
                 status = 0;
                 break;
             }
+            phi2 = phi1;
+            phi1 = phi;
             const double mu = o.sigma * a[0] / q;
             for (int c = tid; c < n + m; c += nt) {
                 if (!colpresent(c)) continue;
@@ -1054,6 +1306,7 @@ struct Frame {
     LPD_INLINE void decode(const Args &a, int f)
     {
         lpdec_stats st = {};
+        ticks_pcg = 0;
         const long long t_start = wall_clock64();
         load_gamma(a, f);
         for (int i = tid; i < n; i += nt) u[i] = g[i] >= 0.0 ? 0.0 : 1.0;   // hard decision
@@ -1120,6 +1373,7 @@ struct Frame {
             if (a.obj) a.obj[f] = ob;
             st.status = status;
             st.ticks_total = wall_clock64() - t_start;
+            st.ticks_pcg = ticks_pcg;
             if (a.stats) a.stats[f] = st;
         }
     }

@@ -142,3 +142,21 @@ def has_stopping_set(code, S: np.ndarray) -> bool:
             if all(len(R & s) != 1 for R in rows):
                 return True
     return False
+
+
+def max_parity_violation(code, u):
+    """Largest violation max(0, 1 - LHS) over every odd-set parity inequality of every check
+    (brute force over the odd subsets), i.e. how far u is outside the fundamental polytope."""
+    worst = 0.0
+    u = np.asarray(u, dtype=np.float64)
+    by_deg = {}
+    for j in range(code.m):
+        by_deg.setdefault(len(code.row(j)), []).append(j)
+    for d, js in by_deg.items():
+        U = np.array([u[code.row(j)] for j in js])            # [checks, d]
+        for V in odd_subsets(d):
+            mask = np.zeros(d, dtype=bool)
+            mask[list(V)] = True
+            lhs = (1.0 - U[:, mask]).sum(axis=1) + U[:, ~mask].sum(axis=1)
+            worst = max(worst, float(np.max(1.0 - lhs)))
+    return max(worst, 0.0)
