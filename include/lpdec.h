@@ -109,7 +109,7 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   PRECOND        1 = triangular preconditioner (Algorithm 7), 0 = the slack columns as
  *                  preconditioning set (a diagonal preconditioner)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
- *                  perturbs the complementarity equation by at most XI_TOL * mu (0.1)
+ *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
  *   IPM_STALL      once the largest of the three IPM error measures is below IPM_STALL but
  *                  has not at least halved over the last two iterations, the LP counts as
  *                  solved (the double-precision floor of a degenerate LP) (1e-7)

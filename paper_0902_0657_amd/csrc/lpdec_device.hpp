@@ -70,17 +70,18 @@ LPD_INLINE float maskflip(float v, bool neg, bool keep)
 // Sum over aligned groups of G lanes (4, 8 or 16) with DPP: quad_perm [1,0,3,2] and
 // [2,3,0,1] within quads, then row_half_mirror and row_mirror. Every lane of a group ends
 // with the same sum (each step adds two operands in either order). All lanes must be active.
+// (every row and bank is enabled and every source lane exists, so no old value is needed)
 template <int CTRL>
 LPD_INLINE double dpp_mov(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 LPD_INLINE float dpp_mov(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 // Makes the compiler materialise v here, so that a load feeding v stays where it is issued
 // (beside the other loads of a step) instead of being sunk into the branch that uses it.

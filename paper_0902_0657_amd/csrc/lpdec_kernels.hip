@@ -141,10 +141,14 @@ size_t static_lds_bytes() { return sizeof(Scratch); }
 template <typename PT, bool HOT_LDS, int MODE>
 static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream_t stream)
 {
+    // the per-thread error state is shared with every other HIP user of the thread: drop an
+    // unread error left by an earlier call so that only this launch is checked below
+    (void)hipGetLastError();
     if (HOT_LDS) {
         // raises the dynamic-LDS limit of this kernel to what the hot arena needs
-        (void)hipFuncSetAttribute((const void *)lpdec_main<PT, HOT_LDS, MODE>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        const hipError_t e = hipFuncSetAttribute((const void *)lpdec_main<PT, HOT_LDS, MODE>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(a.nframes), dim3(block),
                        HOT_LDS ? lds_bytes : 0, stream, a);

@@ -181,7 +181,8 @@ def _n1024_batch():
 
 def test_config2_n1024_full_batch(ctx, orc):
     """The benchmark's launch (512 frames, FP32 LLRs, default precision). Every frame: p <= m
-    (Corollary 3), no numerical failure, u inside the fundamental polytope, a flag-1 frame's
+    (Corollary 3), no numerical failure, u inside the fundamental polytope up to the violation
+    threshold at which MALP stops adding cuts, a flag-1 frame's
     decisions satisfy every check and equal its LP solution. A sample of frames from every
     Eb/N0 group, fractional ones included, is checked against the oracle."""
     import torch
@@ -194,7 +195,8 @@ def test_config2_n1024_full_batch(ctx, orc):
     assert np.all(st[:, 3] <= code.m) and np.all(fl >= 0)
     H = code.dense()
     for f in range(G.shape[0]):
-        assert refs.max_parity_violation(code, u[f]) < 1e-5, f
+        # MALP stops once no inequality is violated by more than TAU_VIOL (1e-4)
+        assert refs.max_parity_violation(code, u[f]) < 1e-4 + 1e-6, f
         if fl[f] == 1:
             assert not ((H @ xh[f]) % 2).any() and np.array_equal(xh[f], (u[f] > 0.5).astype(np.uint8)), f
     # frames 8 and 53 end at the double-precision floor of the IPM; 62 and 153 are fractional
