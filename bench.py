@@ -107,14 +107,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving(ctx, seconds=10.0, qps=None, seed=5):
-    """Poisson arrivals of frames from codes n in {256, 1024, 4096 (3,6); 8192 irregular},
-    Eb/N0 uniform in [1.5, 3.0] dB, through lpdec_server (continuous batching over four
-    streams). Latency = submit to result, per request."""
+def serving(ctx, seconds=10.0, qps=None, seed=5, full=False):
+    """Poisson arrivals of frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through
+    lpdec_server (continuous batching over four streams). Latency = submit to result, per
+    request. Default mix: (3,6) n=256 and n=1024; full: also (3,6) n=4096 and the irregular
+    n=8192 code (their fractional frames take tens of seconds each)."""
     from paper_0902_0657_amd import Code
     from synth.channel import awgn_llr, frame_seed
     from synth.codes import irregular_code, regular_code
-    codes = [regular_code(256), regular_code(1024), regular_code(4096), irregular_code(8192)]
+    codes = [regular_code(256), regular_code(1024)]
+    if full:
+        codes += [regular_code(4096), irregular_code(8192)]
     Cs = [Code.from_synth(ctx, c) for c in codes]
     rng = np.random.Generator(np.random.PCG64(seed))
     srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
@@ -124,7 +127,7 @@ def serving(ctx, seconds=10.0, qps=None, seed=5):
     while time.perf_counter() - t0 < seconds:
         now = time.perf_counter()
         while t_next <= now:
-            ci = int(rng.integers(0, 4))
+            ci = int(rng.integers(0, len(codes)))
             g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(77, ci, k))
             tickets.append((srv.submit(Cs[ci], g), codes[ci].n))
             k += 1
@@ -140,7 +143,8 @@ def serving(ctx, seconds=10.0, qps=None, seed=5):
         fails += r[1] < 0
     srv.close()
     lat = np.array(lat)
-    return {"requests": len(lat), "offered_qps": qps, "arrival_s": seconds, "frames_per_s": len(lat) / wall,
+    return {"codes": [c.name for c in codes], "requests": len(lat), "offered_qps": qps, "arrival_s": seconds,
+            "frames_per_s": len(lat) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "per_code_p50_ms": {str(n): float(np.percentile(v, 50) * 1e3) for n, v in sorted(per.items())},
             "per_code_p99_ms": {str(n): float(np.percentile(v, 99) * 1e3) for n, v in sorted(per.items())},
@@ -204,7 +208,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-PCG leg")
-    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving leg over n = 256, 1024, 4096 and the irregular 8192 code")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB copy first (HBM counter calibration under rocprofv3)")
     ap.add_argument("--block", type=int, default=0)
@@ -327,8 +333,9 @@ def main():
                 if not (np.array_equal(xh, xhat[k]) and fl == flags[k]
                         and abs(ob - objs[k]) <= 1e-6 * (1.0 + abs(ob - float(G[k][G[k] < 0].sum()))))]
         res["parity_sample"] = {"frames": len(done), "mismatches": len(mism)}
-    if args.serve:
-        res["serving"] = serving(ctx)
+    if not args.no_serve:
+        res["serving"] = serving(ctx, full=args.serve_full)
+        log(f"serving: {res['serving']['requests']} requests")
     print(json.dumps(res))
 
 

@@ -69,7 +69,7 @@ typedef struct {
     int32_t max_levels;   /* deepest level schedule of a preconditioner solve */
     int32_t status;       /* 0 or the failing LPDEC_FLAG_* */
     int32_t escalations;  /* Newton solves switched from FP32 to FP64 PCG */
-    int32_t reserved;
+    int32_t direct_solves;/* Newton solves finished by the dense fallback (DIRECT_FALLBACK) */
     int64_t pcg_rows;     /* sum over PCG iterations of the LP's row count p */
     int64_t ipm_cols;     /* sum over IPM iterations of the LP's column count q = n + p */
     int64_t ticks_mts;    /* device clock ticks (100 MHz) in the triangular-set search */
@@ -110,6 +110,10 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  preconditioning set (a diagonal preconditioner)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
+ *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
+ *                  XI_TOL goal is solved again by a dense Cholesky factorisation of
+ *                  A D^2 A^T on the GPU (FP64, in the frame's global workspace, 8 m^2 bytes
+ *                  per frame); 0 = keep the PCG result
  *   IPM_STALL      once the largest of the three IPM error measures is below IPM_STALL but
  *                  has not at least halved over the last two iterations, the LP counts as
  *                  solved (the double-precision floor of a degenerate LP) (1e-7)
@@ -119,7 +123,7 @@ enum {
     LPDEC_OPT_TAU_INT, LPDEC_OPT_IPM_EPS, LPDEC_OPT_SIGMA, LPDEC_OPT_ETA, LPDEC_OPT_PCG_TOL,
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
-    LPDEC_OPT_IPM_STALL, LPDEC_OPT__COUNT
+    LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);
@@ -174,8 +178,8 @@ lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int3
  * ordered by (weight descending, column index ascending). Outputs: pair_dev int32[nframes*m]
  * = column matched to row j (-1 for checks without a cut); lev_b_dev / lev_f_dev
  * int32[nframes*m] = dependency level of row j in the back- and forward-substitution of the
- * preconditioner solve (-1 without a cut); rounds_dev int32[nframes] (nullable) = parallel
- * rounds used. */
+ * preconditioner solve (-1 without a cut); rounds_dev int32[nframes] (nullable) = greedy
+ * steps taken (one per LP row, p). */
 lpdec_status lpdec_mts_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
                              const uint8_t *hascut_dev, const float *w_dev, int32_t *pair_dev,
                              int32_t *lev_b_dev, int32_t *lev_f_dev, int32_t *rounds_dev);

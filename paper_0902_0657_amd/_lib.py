@@ -13,14 +13,14 @@ FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT = -1, -2, -3, -4
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",
-    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL"])}
+    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL", "DIRECT_FALLBACK"])}
 
 
 class Stats(C.Structure):
     _fields_ = [("malp_iters", C.c_int32), ("ipm_iters", C.c_int32), ("pcg_iters", C.c_int32),
                 ("p_max", C.c_int32), ("ref_rounds", C.c_int32), ("mts_rounds", C.c_int32),
                 ("max_levels", C.c_int32), ("status", C.c_int32), ("escalations", C.c_int32),
-                ("reserved", C.c_int32), ("pcg_rows", C.c_int64),
+                ("direct_solves", C.c_int32), ("pcg_rows", C.c_int64),
                 ("ipm_cols", C.c_int64), ("ticks_mts", C.c_int64), ("ticks_solve", C.c_int64),
                 ("ticks_total", C.c_int64), ("ticks_pcg", C.c_int64)]
 

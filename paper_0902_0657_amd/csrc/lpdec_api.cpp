@@ -101,6 +101,7 @@ void default_opts(lpdec::Opts &o)
     o.pcg_maxit = 500;
     o.ref_max = 3;
     o.precond = 1;
+    o.direct = 1;
     o.tau_viol = 1e-4;
     o.tau_act = 1e-4;
     o.tau_int = 1e-4;
@@ -139,7 +140,9 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     if (a.nframes <= 0) return LPDEC_OK;
     a.code = view(code);
     a.o = ctx->opts;
-    a.plan = lpdec::make_plan(code->m, code->n, code->dcmax, code->dvmax, pt64 ? 8 : 4);
+    // the dense fallback exists only inside the IPM (decode and IPM modes)
+    const bool dense = ctx->opts.direct && (a.mode == lpdec::MODE_DECODE || a.mode == lpdec::MODE_IPM);
+    a.plan = lpdec::make_plan(code->m, code->n, code->dcmax, code->dvmax, pt64 ? 8 : 4, dense);
     const size_t lds_need = a.plan.hot_bytes;
     const size_t lds_avail = (size_t)ctx->lds_limit - lpdec::static_lds_bytes() - 256;
     a.hot_in_lds = lds_need <= lds_avail;
@@ -229,6 +232,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_PRECOND: if (v != 0 && v != 1) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
     case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;
+    case LPDEC_OPT_DIRECT_FALLBACK: if (v != 0 && v != 1) break; o.direct = (int)v; return LPDEC_OK;
     default: return fail(ctx, LPDEC_EINVAL, "unknown option key %d", key);
     }
     return fail(ctx, LPDEC_EINVAL, "bad value %g for option %d", v, key);
@@ -257,6 +261,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_PRECOND: *v = o.precond; break;
     case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
     case LPDEC_OPT_IPM_STALL: *v = o.eps_stall; break;
+    case LPDEC_OPT_DIRECT_FALLBACK: *v = o.direct; break;
     default: return LPDEC_EINVAL;
     }
     return LPDEC_OK;
@@ -554,7 +559,7 @@ namespace {
 
 size_t frame_footprint(const lpdec_code *c, int pt64)
 {
-    Plan p = lpdec::make_plan(c->m, c->n, c->dcmax, c->dvmax, pt64 ? 8 : 4);
+    Plan p = lpdec::make_plan(c->m, c->n, c->dcmax, c->dvmax, pt64 ? 8 : 4, c->ctx->opts.direct != 0);
     // cold arena + hot arena (counted even when it lives in LDS) + gamma + outputs
     return p.cold_bytes + p.hot_bytes + 8 * (size_t)c->n + (size_t)c->n + 64;
 }

@@ -15,6 +15,7 @@ struct Opts {
     int pcg_maxit;
     int ref_max;
     int precond;     // 1: triangular preconditioner, 0: M = I
+    int direct;      // 1: dense Cholesky fallback for Newton solves PCG does not finish
     double tau_viol, tau_act, tau_int;
     double eps, eps_stall, sigma, eta;
     double pcg_tol, ref_tol, xi_tol;
@@ -40,6 +41,7 @@ struct CodeView {
 struct Plan {
     int rw, cw;                                // slot widths (entries)
     int lanecols, maskwords;                   // columns per lane of Algorithm 7, mask words
+    int dense_on;                              // the dense fallback region exists
     // hot
     size_t h, r, v, l, idm, om, st, d2f;       // PT: [m] x 6, st [m + (n+m) + 1], d2f [n+m]
     size_t rlist, clist, bins, fins;           // u16 [m*rw], [n*cw], [m*rw], [m*cw]
@@ -54,6 +56,7 @@ struct Plan {
     size_t y, dy, rb, w, b, rho, f64;          // [m]
     size_t c64;                                // 8 x [m]: FP64 PCG vectors (escalation), dy copy
     size_t st64;                               // [m + (n+m) + 1]: s | t of the escalated PCG
+    size_t ridx, colk, dense;                  // dense fallback: i32 [m+1], FP64 [m], FP64 [m*m]
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
     size_t cold_bytes;
@@ -68,7 +71,7 @@ __host__ __device__ inline int lp_pow2_at_least(int v, int lo)
     return w;
 }
 
-__host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_size)
+__host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_size, bool dense = false)
 {
     Plan p;
     // a row slot holds a header and up to dc entries (row lists: dc columns), a column slot
@@ -123,6 +126,10 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.f64 = o; o = lp_align(o + 8 * M);
     p.c64 = o; o = o + 8 * lp_align(8 * M);
     p.st64 = o; o = lp_align(o + 8 * (M + Q + 1));
+    p.dense_on = dense ? 1 : 0;
+    p.ridx = o; o = lp_align(o + 4 * (M + 1));
+    p.colk = o; o = lp_align(o + 8 * M);
+    p.dense = o; o = lp_align(o + (dense ? 8 * M * M : 0));
     p.u = o; o = lp_align(o + 8 * N);
     p.g = o; o = lp_align(o + 8 * N);
     p.active = o; o = lp_align(o + M);

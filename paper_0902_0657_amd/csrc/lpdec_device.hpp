@@ -426,6 +426,8 @@ struct Frame {
     double *x, *z, *dx, *dz, *rc, *tq, *d2, *y, *dy, *rb, *w, *b, *rho, *f64, *u, *g;
     double *c64[8];   // FP64 PCG vectors for escalated solves, and a copy of dy
     double *st64;     // s | t | 0 of the escalated FP64 PCG
+    int *ridx;        // dense fallback: LP row index of each check
+    double *colk, *qd;   // dense fallback: work vector, the p x p matrix (null when absent)
     uint8_t *active;
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
@@ -444,6 +446,9 @@ struct Frame {
         t = s + m; d2f = (PT *)(hot + P.d2f);
         Z = n + 2 * m;
         st64 = (double *)(cold + P.st64);
+        ridx = (int *)(cold + P.ridx);
+        colk = (double *)(cold + P.colk);
+        qd = P.dense_on ? (double *)(cold + P.dense) : nullptr;
         rlist = (uint16_t *)(hot + P.rlist); clist = (uint16_t *)(hot + P.clist);
         bins = (uint16_t *)(hot + P.bins); fins = (uint16_t *)(hot + P.fins);
         pair = (int16_t *)(hot + P.pair); pairrow = (int16_t *)(hot + P.pairrow);
@@ -1087,8 +1092,9 @@ struct Frame {
     // Returns PCG iterations; refine_rounds counts the extra rounds, escal the switches;
     // resid2 = ||rho||^2 / ||w||^2. On return rho holds the final residual and, when mu > 0,
     // f64 holds A_M^-1 rho.
-    LPD_INLINE int solve(double mu, int &refine_rounds, int &escal, double &resid2)
+    LPD_INLINE int solve(double mu, int &refine_rounds, int &escal, double &resid2, bool &met)
     {
+        met = true;
         double nw2 = 0.0;
         for (int j = tid; j < m; j += nt) {
             const double wj = cut(j) ? w[j] : 0.0;
@@ -1128,6 +1134,7 @@ struct Frame {
             resid2 = nr2 / nw2;
             const bool done = use_xi ? (err <= xi_goal || nr2 <= o.ref_tol * o.ref_tol * nw2)
                                      : (nr2 <= o.ref_tol * o.ref_tol * nw2);
+            met = done;
             if (done || !(err == err)) break;
             if (!wide && (err > (use_xi ? 0.5 : 0.25) * prev || left <= 0)) {
                 wide = 1;
@@ -1142,6 +1149,87 @@ struct Frame {
             ++refine_rounds;
         }
         return its;
+    }
+
+    // Dense fallback for a Newton system the PCG rounds did not finish: Q = A D^2 A^T over the
+    // LP rows (ascending check order) assembled in the frame's global workspace, factorised
+    // in place by Cholesky (lower triangle, row-major; a pivot that is not above 1e-30 of the
+    // largest diagonal entry becomes 1e128, which sets its component to about zero), then
+    // forward and back substitution. Writes dy; the caller recomputes the FP64 residual.
+    LPD_INLINE void direct_solve()
+    {
+        for (int j = tid; j < m; j += nt) ridx[j] = cut(j) ? 1 : 0;
+        block_exscan(ridx, m);
+        const int P = ridx[m];
+        double *const Q = qd;
+        for (size_t t = tid; t < (size_t)P * P; t += nt) Q[t] = 0.0;
+        __syncthreads();
+        // lower triangle, one thread per LP row: row r gets a_ri a_r'i d_i^2 for every column i
+        // of the row and every row r' <= r of that column, and the row's slack weight
+        double dm = 0.0;
+        for (int j = tid; j < m; j += nt) {
+            if (!cut(j)) continue;
+            const int r = ridx[j];
+            double *const Qr = Q + (size_t)r * P;
+            double diag = d2[n + j];
+            for (int k = 0; k < RW; ++k) {
+                const uint16_t e = rlist[(size_t)j * RW + k];
+                if (e == kEnd) break;
+                const int i = e_idx(e);
+                const double di = d2[i];
+                for (int q = 0; q < CW; ++q) {
+                    const uint16_t e2 = clist[(size_t)i * CW + q];
+                    if (e2 == kEnd) break;
+                    const int j2 = e_idx(e2);
+                    if (j2 == j) { diag += di; continue; }
+                    const int r2 = ridx[j2];
+                    if (r2 < r) Qr[r2] += (e_neg(e) != e_neg(e2) ? -di : di);
+                }
+            }
+            Qr[r] = diag;
+            dm = fmax(dm, diag);
+        }
+        dm = block_max_d(dm, sc);
+        for (int k = 0; k < P; ++k) {
+            double *const Qk = Q + (size_t)k * P;
+            double s = Qk[k];
+            if (!(s > 1e-30 * dm)) s = 1e128;
+            const double lkk = sqrt(s);
+            for (int i = k + 1 + tid; i < P; i += nt) {
+                const double v = Q[(size_t)i * P + k] / lkk;
+                Q[(size_t)i * P + k] = v;
+                colk[i] = v;
+            }
+            __syncthreads();
+            if (tid == 0) Qk[k] = lkk;
+            for (int i = k + 1; i < P; ++i) {
+                const double ci = colk[i];
+                double *const Qi = Q + (size_t)i * P;
+                for (int jj = k + 1 + tid; jj <= i; jj += nt) Qi[jj] -= ci * colk[jj];
+            }
+            __syncthreads();
+        }
+        // L y = w, then L^T x = y (in colk, indexed by LP row)
+        for (int j = tid; j < m; j += nt)
+            if (cut(j)) colk[ridx[j]] = w[j];
+        __syncthreads();
+        for (int c = 0; c < P; ++c) {
+            const double yc = colk[c] / Q[(size_t)c * P + c];
+            __syncthreads();
+            if (tid == 0) colk[c] = yc;
+            for (int r = c + 1 + tid; r < P; r += nt) colk[r] -= Q[(size_t)r * P + c] * yc;
+            __syncthreads();
+        }
+        for (int c = P - 1; c >= 0; --c) {
+            const double xc = colk[c] / Q[(size_t)c * P + c];
+            __syncthreads();
+            if (tid == 0) colk[c] = xc;
+            for (int r = tid; r < c; r += nt) colk[r] -= Q[(size_t)c * P + r] * xc;
+            __syncthreads();
+        }
+        for (int j = tid; j < m; j += nt)
+            if (cut(j)) dy[j] = colk[ridx[j]];
+        __syncthreads();
     }
 
     LPD_INLINE void set_d2f(int c, double dd)
@@ -1197,6 +1285,9 @@ struct Frame {
         const double q = (double)(n + p);
         int status = LPDEC_FLAG_IPM_CAP, it;
         double phi1 = INFINITY, phi2 = INFINITY;   // error measure one and two iterations ago
+        // set once PCG has failed on this LP: its later Newton systems are only worse
+        // conditioned, so they go straight to the dense solve
+        bool direct_mode = false;
         for (it = 0; it < o.ipm_max; ++it) {
             double a[4] = {0.0, 0.0, 0.0, 0.0};   // gap, c^T x, ||r_b||^2, ||r_c||^2
             for (int j = tid; j < m; j += nt) {
@@ -1242,17 +1333,30 @@ struct Frame {
                 if (cut(j)) w[j] = rb[j] + row_dot<double>(j, tq);
             // preconditioner for this iteration (Sec. V-B: found anew at every iteration)
             const long long t0 = wall_clock64();
-            if (o.precond) mts(nullptr);
-            else slack_basis();
-            build_levels();
-            st.max_levels = max(st.max_levels, max(nlb, nlf));
+            if (!direct_mode) {
+                if (o.precond) mts(nullptr);
+                else slack_basis();
+                build_levels();
+                st.max_levels = max(st.max_levels, max(nlb, nlf));
+            }
             const long long t1 = wall_clock64();
-            double resid2;
-            const int pits = solve(mu, st.ref_rounds, st.escalations, resid2);
+            double resid2 = 0.0;
+            bool met = true;
+            const int pits = direct_mode ? 0 : solve(mu, st.ref_rounds, st.escalations, resid2, met);
+            if ((direct_mode || !met) && qd) {
+                // PCG did not reach the goal (now or earlier in this LP): the Newton system is
+                // solved directly; its residual is at rounding level, so the completion below
+                // gets no correction term
+                direct_solve();
+                for (int j = tid; j < m; j += nt) f64[j] = 0.0;
+                __syncthreads();
+                ++st.direct_solves;
+                direct_mode = true;
+            }
             const long long t2 = wall_clock64();
             st.ticks_mts += t1 - t0;
             st.ticks_solve += t2 - t1;
-            st.mts_rounds += o.precond ? p : 0;
+            st.mts_rounds += o.precond && !direct_mode ? p : 0;
             st.pcg_iters += pits;
             st.pcg_rows += (long long)pits * p;
             st.ipm_cols += n + p;

@@ -56,7 +56,8 @@ LPD_INLINE void run_solve(Frame<PT> &F, const Args &a, int f)
     F.build_levels();
     int refr = 0, escal = 0;
     double resid2 = 0.0;
-    const int its = F.solve(0.0, refr, escal, resid2);
+    bool met;
+    const int its = F.solve(0.0, refr, escal, resid2, met);
     for (int j = F.tid; j < m; j += F.nt) a.vec_out[(size_t)f * m + j] = F.cut(j) ? F.dy[j] : 0.0;
     if (F.tid == 0) {
         if (a.i_out) a.i_out[f] = its;

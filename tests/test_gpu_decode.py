@@ -204,3 +204,26 @@ def test_config2_n1024_full_batch(ctx, orc):
     sample = [0, 1, 2, 8, 53, 62, 153, 171, 172, 173, 342, 343, 344]
     flat = _compare(orc, code, G.astype(np.float64), out, oracle_frames=sample, allow_flat=True)
     print("decisions on a flat optimal face:", flat)
+
+
+def test_dense_fallback_path(ctx, orc):
+    """With a PCG budget of 2 iterations every Newton solve misses its goal, so every LP after
+    its first Newton step runs on the dense Cholesky fallback: that path alone must decode
+    like the oracle."""
+    import torch
+    code = regular_code(256)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 1.5, 24, stream=9)
+    ctx.set_option("PCG_MAXIT", 2)
+    ctx.set_option("REF_MAX", 0)
+    try:
+        out = ctx.decode_batch(C, cuda(G, torch.float64))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("PCG_MAXIT", 500)
+        ctx.set_option("REF_MAX", 3)
+    st = host(out["stats"])
+    from paper_0902_0657_amd import stats_table
+    s = stats_table(st)
+    assert np.all(s["direct_solves"][s["malp_iters"] > 0] > 0)
+    _compare(orc, code, G, out)

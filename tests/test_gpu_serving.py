@@ -11,9 +11,9 @@ from tests.gpu_util import cuda, host, make_ctx, obj_close
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("budget_mb,slots", [(512, 256), (2, 6)])
+@pytest.mark.parametrize("budget_mb,slots", [(512, 256), (8, 6)])
 def test_mixed_lengths_match_alone(orc, budget_mb, slots):
-    """The second case admits only a handful of frames at a time (2 MB of workspace, 6
+    """The second case admits only a handful of frames at a time (8 MB of workspace, 6
     slots), so later requests wait for earlier ones to retire."""
     import torch
     from paper_0902_0657_amd import Code
