@@ -275,7 +275,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if fp64 else "f32 PCG / f64 IPM", "data": "synthetic",
         "config": {"workload": "(3,6)-regular LDPC n=1024 m=512, AWGN Eb/N0 1.5/2.0/2.5 dB "
                                "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
-                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " with FP64 refinement",
+                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " with FP64 refinement, "
+                               "dense Cholesky for Newton systems PCG does not finish",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "batch mode: a frame's result is available when its launch ends"},
@@ -291,7 +292,9 @@ def main():
                          "max_p": int(st["p_max"].max()), "max_levels": int(st["max_levels"].max()),
                          "pcg_us_per_iteration": float(st["ticks_pcg"].sum() / 100.0 / max(1, st["pcg_iters"].sum())),
                          "mts_us_per_ipm_iteration": float(st["ticks_mts"].sum() / 100.0 / max(1, st["ipm_iters"].sum())),
-                         "ref_rounds": int(st["ref_rounds"].sum())},
+                         "ref_rounds": int(st["ref_rounds"].sum()),
+                         "dense_fallback_solves": int(st["direct_solves"].sum()),
+                         "newton_solves": int(st["ipm_iters"].sum())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,

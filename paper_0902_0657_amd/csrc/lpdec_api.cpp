@@ -143,7 +143,8 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     // the dense fallback exists only inside the IPM (decode and IPM modes)
     const bool dense = ctx->opts.direct && (a.mode == lpdec::MODE_DECODE || a.mode == lpdec::MODE_IPM);
     a.plan = lpdec::make_plan(code->m, code->n, code->dcmax, code->dvmax, pt64 ? 8 : 4, dense);
-    const size_t lds_need = a.plan.hot_bytes;
+    const size_t lds_dense = a.plan.dense_on ? lpdec::kDenseLdsBytes : 0;
+    const size_t lds_need = lpdec::lp_align(a.plan.hot_bytes) + lds_dense;
     const size_t lds_avail = (size_t)ctx->lds_limit - lpdec::static_lds_bytes() - 256;
     a.hot_in_lds = lds_need <= lds_avail;
     a.hot_stride = a.hot_in_lds ? 0 : lpdec::lp_align(a.plan.hot_bytes + 255) & ~(size_t)255;
@@ -154,7 +155,7 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     a.cold_ws = ws.ptr;
     a.hot_ws = ws.ptr + a.cold_stride * (size_t)a.nframes;
     int block = ctx->block > 0 ? ctx->block : auto_block(code);
-    e = lpdec::launch_main(a, pt64, block, a.hot_in_lds ? lds_need : 0, stream);
+    e = lpdec::launch_main(a, pt64, block, a.hot_in_lds ? lds_need : lds_dense, stream);
     if (e != hipSuccess) return hipfail(ctx, e, "kernel launch");
     return LPDEC_OK;
 }

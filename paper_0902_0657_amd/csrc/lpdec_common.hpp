@@ -64,6 +64,10 @@ struct Plan {
 
 __host__ __device__ inline size_t lp_align(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// LDS tiles of the dense fallback: the diagonal block and two panel tiles, 32 x 32 FP64 each
+constexpr int kDenseTile = 32;
+constexpr size_t kDenseLdsBytes = 3 * kDenseTile * kDenseTile * 8;
+
 __host__ __device__ inline int lp_pow2_at_least(int v, int lo)
 {
     int w = lo;

@@ -428,6 +428,7 @@ struct Frame {
     double *st64;     // s | t | 0 of the escalated FP64 PCG
     int *ridx;        // dense fallback: LP row index of each check
     double *colk, *qd;   // dense fallback: work vector, the p x p matrix (null when absent)
+    double *ldsd;        // dense fallback: three kDenseTile^2 tiles in LDS (set by the kernel)
     uint8_t *active;
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
@@ -1151,6 +1152,89 @@ struct Frame {
         return its;
     }
 
+    // Blocked right-looking Cholesky of the P x P lower triangle of Q (row-major, in global
+    // memory), in place. Per block column of width T = kDenseTile: the diagonal block is
+    // factorised in LDS, the panel rows below it are solved against it one row per thread, and
+    // the trailing lower triangle is updated tile by tile from two panel tiles staged in LDS.
+    // The pivot rule: a pivot not above 1e-30 dm becomes 1e128.
+    LPD_INLINE void chol_blocked(double *Q, int P, double dm)
+    {
+        constexpr int T = kDenseTile;
+        double *const D = ldsd, *const PA = ldsd + T * T, *const PB = ldsd + 2 * T * T;
+        for (int K = 0; K < P; K += T) {
+            const int kb = min(T, P - K);
+            for (int t = tid; t < T * T; t += nt) {
+                const int r = t / T, c = t - r * T;
+                D[t] = (r < kb && c <= r) ? Q[(size_t)(K + r) * P + K + c] : 0.0;
+            }
+            __syncthreads();
+            for (int c = 0; c < kb; ++c) {
+                if (tid == 0) {
+                    double s = D[c * T + c];
+                    if (!(s > 1e-30 * dm)) s = 1e128;
+                    D[c * T + c] = sqrt(s);
+                }
+                __syncthreads();
+                const double lcc = D[c * T + c];
+                for (int r = c + 1 + tid; r < kb; r += nt) D[r * T + c] /= lcc;
+                __syncthreads();
+                const int w = kb - c - 1;
+                for (int t = tid; t < w * w; t += nt) {
+                    const int rr = c + 1 + t / w, cc = c + 1 + t % w;
+                    if (cc <= rr) D[rr * T + cc] -= D[rr * T + c] * D[cc * T + c];
+                }
+                __syncthreads();
+            }
+            for (int t = tid; t < kb * kb; t += nt) {
+                const int r = t / kb, c = t - r * kb;
+                if (c <= r) Q[(size_t)(K + r) * P + K + c] = D[r * T + c];
+            }
+            // panel: row i solves x L_KK^T = a
+            for (int i = K + kb + tid; i < P; i += nt) {
+                double *const Qi = Q + (size_t)i * P + K;
+                for (int c = 0; c < kb; ++c) {
+                    double v = Qi[c];
+                    for (int t = 0; t < c; ++t) v -= Qi[t] * D[c * T + t];
+                    Qi[c] = v / D[c * T + c];
+                }
+            }
+            __syncthreads();
+            // trailing update of rows and columns >= R0: tile row tI keeps its panel tile PA
+            // while the tiles tJ <= tI stream through PB; each thread accumulates 2 x 2 blocks
+            const int R0 = K + kb, nT = (P - R0 + T - 1) / T;
+            for (int tI = 0; tI < nT; ++tI) {
+                const int I0 = R0 + tI * T;
+                for (int t = tid; t < T * T; t += nt) {
+                    const int r = t / T, c = t - r * T;
+                    PA[t] = (c < kb && I0 + r < P) ? Q[(size_t)(I0 + r) * P + K + c] : 0.0;
+                }
+                for (int tJ = 0; tJ <= tI; ++tJ) {
+                    const int J0 = R0 + tJ * T;
+                    for (int t = tid; t < T * T; t += nt) {
+                        const int r = t / T, c = t - r * T;
+                        PB[t] = (c < kb && J0 + r < P) ? Q[(size_t)(J0 + r) * P + K + c] : 0.0;
+                    }
+                    __syncthreads();
+                    for (int b = tid; b < (T / 2) * (T / 2); b += nt) {
+                        const int r = 2 * (b / (T / 2)), c = 2 * (b % (T / 2));
+                        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+                        for (int k = 0; k < kb; ++k) {
+                            const double x0 = PA[r * T + k], x1 = PA[(r + 1) * T + k];
+                            const double y0 = PB[c * T + k], y1 = PB[(c + 1) * T + k];
+                            a00 += x0 * y0; a01 += x0 * y1; a10 += x1 * y0; a11 += x1 * y1;
+                        }
+                        const int gi = I0 + r, gj = J0 + c;
+                        if (gi < P && gj <= gi) Q[(size_t)gi * P + gj] -= a00;
+                        if (gi < P && gj + 1 <= gi) Q[(size_t)gi * P + gj + 1] -= a01;
+                        if (gi + 1 < P && gj <= gi + 1) Q[(size_t)(gi + 1) * P + gj] -= a10;
+                        if (gi + 1 < P && gj + 1 <= gi + 1) Q[(size_t)(gi + 1) * P + gj + 1] -= a11;
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+
     // Dense fallback for a Newton system the PCG rounds did not finish: Q = A D^2 A^T over the
     // LP rows (ascending check order) assembled in the frame's global workspace, factorised
     // in place by Cholesky (lower triangle, row-major; a pivot that is not above 1e-30 of the
@@ -1190,25 +1274,7 @@ struct Frame {
             dm = fmax(dm, diag);
         }
         dm = block_max_d(dm, sc);
-        for (int k = 0; k < P; ++k) {
-            double *const Qk = Q + (size_t)k * P;
-            double s = Qk[k];
-            if (!(s > 1e-30 * dm)) s = 1e128;
-            const double lkk = sqrt(s);
-            for (int i = k + 1 + tid; i < P; i += nt) {
-                const double v = Q[(size_t)i * P + k] / lkk;
-                Q[(size_t)i * P + k] = v;
-                colk[i] = v;
-            }
-            __syncthreads();
-            if (tid == 0) Qk[k] = lkk;
-            for (int i = k + 1; i < P; ++i) {
-                const double ci = colk[i];
-                double *const Qi = Q + (size_t)i * P;
-                for (int jj = k + 1 + tid; jj <= i; jj += nt) Qi[jj] -= ci * colk[jj];
-            }
-            __syncthreads();
-        }
+        chol_blocked(Q, P, dm);
         // L y = w, then L^T x = y (in colk, indexed by LP row)
         for (int j = tid; j < m; j += nt)
             if (cut(j)) colk[ridx[j]] = w[j];

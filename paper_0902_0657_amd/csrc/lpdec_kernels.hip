@@ -129,6 +129,8 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
     char *cold = a.cold_ws + (size_t)f * a.cold_stride;
     Frame<PT> F;
     F.bind(a, hot, cold, &sc);
+    // tiles of the dense fallback follow the hot arena in dynamic LDS
+    F.ldsd = a.plan.dense_on ? (double *)(lds_dyn + (HOT_LDS ? lp_align(a.plan.hot_bytes) : 0)) : nullptr;
     if constexpr (MODE == MODE_DECODE) F.decode(a, f);
     else if constexpr (MODE == MODE_IPM) run_ipm(F, a, f);
     else if constexpr (MODE == MODE_SOLVE) run_solve(F, a, f);
@@ -145,14 +147,14 @@ static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream
     // the per-thread error state is shared with every other HIP user of the thread: drop an
     // unread error left by an earlier call so that only this launch is checked below
     (void)hipGetLastError();
-    if (HOT_LDS) {
-        // raises the dynamic-LDS limit of this kernel to what the hot arena needs
+    if (lds_bytes > 0) {
+        // raises the dynamic-LDS limit of this kernel to what the hot arena and the dense
+        // fallback's tiles need
         const hipError_t e = hipFuncSetAttribute((const void *)lpdec_main<PT, HOT_LDS, MODE>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(a.nframes), dim3(block),
-                       HOT_LDS ? lds_bytes : 0, stream, a);
+    hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(a.nframes), dim3(block), lds_bytes, stream, a);
     return hipGetLastError();
 }
 
