@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 N, SNRS, SPLIT = 1024, (1.5, 2.0, 2.5), (171, 171, 170)
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6     # dense FP64 matrix-core peak of the chip
 
 
 def workload():
@@ -45,6 +46,11 @@ def algorithmic_bytes(st, n):
     pcg_its = st["pcg_iters"].astype(np.float64)
     ipm_cols = st["ipm_cols"].astype(np.float64)
     return float(np.sum(27 * pcg_rows + 4 * (pcg_its * n + pcg_rows) + 120 * ipm_cols))
+
+
+def dense_flops(st):
+    """Flops of the dense-fallback Cholesky factorizations: P^3 / 3 per solve (P padded)."""
+    return float(st["dense_cube"].astype(np.float64).sum() / 3.0)
 
 
 def _oracle_worker(args):
@@ -209,6 +215,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-PCG leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-pcg-primary", action="store_true",
+                    help="skip the leg with a fixed PCG cap of 500 (dense solves only for systems PCG fails)")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg over n = 256, 1024, 4096 and the irregular 8192 code")
     ap.add_argument("--calib-copy", action="store_true",
@@ -268,6 +276,23 @@ def main():
     achieved = alg / kern_s / 1e9
     traffic, traffic_note = stored_traffic()
     frame_ms = st["ticks_total"].astype(np.float64) / 1e5   # 100 MHz device clock
+    flops = dense_flops(st)
+    tf = flops / kern_s / 1e12
+    pcg_share = float(st["ticks_pcg"].sum() / max(1, st["ticks_total"].sum()))
+    dense_share = float(st["ticks_dense"].sum() / max(1, st["ticks_total"].sum()))
+    hbm_view = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,
+                "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
+                "algorithmic_bytes_per_launch": alg,
+                "basis": "PCG iterations 27p + 4q bytes, IPM iterations 120q bytes"}
+    mfma_view = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                 "frac": tf / FP64_PEAK_TFS, "traffic": None, "algorithmic_flops_per_launch": flops,
+                 "basis": "dense-fallback Cholesky, P^3/3 flops per solve, FP64 matrix cores"}
+    # the roofline of the work that takes most of the device time; the other one beside it
+    primary, secondary = (mfma_view, hbm_view) if dense_share > pcg_share else (hbm_view, mfma_view)
+    kname = f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>"
+    primary.update({"kernel": kname, "kernel_ms": kern_s * 1e3})
     res = {
         "metric": "LP-decoded frames/s at n=1024 (3,6) + p50/p99 latency, vs plain FP64 GPU",
         "value": value, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -275,8 +300,10 @@ def main():
         "vs_baseline": None, "dtype": "f64" if fp64 else "f32 PCG / f64 IPM", "data": "synthetic",
         "config": {"workload": "(3,6)-regular LDPC n=1024 m=512, AWGN Eb/N0 1.5/2.0/2.5 dB "
                                "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
-                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " with FP64 refinement, "
-                               "dense Cholesky for Newton systems PCG does not finish",
+                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " (Algorithm 4, Algorithm 7 "
+                               "preconditioner) with FP64 refinement first; once PCG misses its goal within "
+                               "the automatic cap (about p^2/7000 iterations) the LP's remaining Newton systems "
+                               "go to dense FP64 Cholesky on the matrix cores",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "batch mode: a frame's result is available when its launch ends"},
@@ -294,13 +321,12 @@ def main():
                          "mts_us_per_ipm_iteration": float(st["ticks_mts"].sum() / 100.0 / max(1, st["ipm_iters"].sum())),
                          "ref_rounds": int(st["ref_rounds"].sum()),
                          "dense_fallback_solves": int(st["direct_solves"].sum()),
-                         "newton_solves": int(st["ipm_iters"].sum())},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,
-                     "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
-                     "kernel": f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>",
-                     "algorithmic_bytes_per_launch": alg, "kernel_ms": kern_s * 1e3},
+                         "newton_solves": int(st["ipm_iters"].sum()),
+                         "newton_solved_by_pcg": 1.0 - float(st["direct_solves"].sum() / max(1, st["ipm_iters"].sum())),
+                         "device_time_share": {"pcg": pcg_share, "dense_fallback": dense_share,
+                                               "mts": float(st["ticks_mts"].sum() / max(1, st["ticks_total"].sum()))}},
+        "roofline": primary,
+        "roofline_other": secondary,
     }
     if not args.no_fp32 and fp64:
         c32 = Context(0)
@@ -320,6 +346,26 @@ def main():
                                                         or not np.array_equal(x32[f], xhat[f])))}
         log(f"fp32 PCG leg: {ms32:.1f} ms")
         c32.close()
+    if not args.no_pcg_primary:
+        cp = Context(0)
+        cp.set_option("PCG_MAXIT", 500)
+        Cp = Code.from_synth(cp, code)
+        op = cp.batch_outputs(Cp, nf, dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cp.decode_batch(Cp, g, out=op, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        msp = e0.elapsed_time(e1)
+        sp = stats_table(op["stats"])
+        fp_, xp = op["flag"].cpu().numpy(), op["xhat"].cpu().numpy()
+        res["pcg_primary"] = {"value": nf / (msp / 1e3), "unit": "frames/s", "ms_per_step": msp,
+                              "pcg_maxit": 500,
+                              "newton_solved_by_pcg": 1.0 - float(sp["direct_solves"].sum() / max(1, sp["ipm_iters"].sum())),
+                              "differs_from_main": int(sum(1 for f in range(nf) if fp_[f] != flags[f]
+                                                           or not np.array_equal(xp[f], xhat[f])))}
+        log(f"PCG-primary leg: {msp:.1f} ms")
+        cp.close()
     if not args.no_plain:
         frames = [g0 + k for k in range(8) for g0 in (0, 171, 342)]
         pf, plain_res = plain_fp64(ctx, C, G, frames)

@@ -76,6 +76,8 @@ typedef struct {
     int64_t ticks_solve;  /* ticks in the Newton solves (PCG, refinement) */
     int64_t ticks_total;  /* ticks of the whole decode of the frame */
     int64_t ticks_pcg;    /* ticks inside PCG iterations (part of ticks_solve) */
+    int64_t ticks_dense;  /* ticks in dense-fallback solves (part of ticks_solve) */
+    int64_t dense_cube;   /* sum over dense-fallback solves of P^3, P = LP rows padded to 32 */
 } lpdec_stats;
 
 /* ---- context ---------------------------------------------------------------------- */
@@ -100,7 +102,9 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   SIGMA          centering factor: mu = SIGMA * x^T z / q (0.1)
  *   ETA            fraction-to-boundary factor of the step lengths (0.9995)
  *   PCG_TOL        PCG stops at ||r|| <= PCG_TOL ||rhs|| (1e-6)
- *   PCG_MAXIT      PCG iteration cap per solve (500)
+ *   PCG_MAXIT      PCG iteration cap per round; 0 (default) = automatic: with the dense
+ *                  fallback, min(2000, max(20, p^2 / 7000)) for an LP of p rows (about the
+ *                  PCG iterations that cost as much as one dense solve), else 500
  *   REF_TOL        refinement of dy stops at ||w - Q dy|| <= REF_TOL ||w|| (1e-10)
  *   REF_MAX        refinement rounds after the first solve (3)
  *   IPM_MAX        IPM iteration cap per LP (100)

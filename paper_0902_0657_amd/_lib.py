@@ -22,7 +22,8 @@ class Stats(C.Structure):
                 ("max_levels", C.c_int32), ("status", C.c_int32), ("escalations", C.c_int32),
                 ("direct_solves", C.c_int32), ("pcg_rows", C.c_int64),
                 ("ipm_cols", C.c_int64), ("ticks_mts", C.c_int64), ("ticks_solve", C.c_int64),
-                ("ticks_total", C.c_int64), ("ticks_pcg", C.c_int64)]
+                ("ticks_total", C.c_int64), ("ticks_pcg", C.c_int64),
+                ("ticks_dense", C.c_int64), ("dense_cube", C.c_int64)]
 
 
 STATS_FIELDS = [f[0] for f in Stats._fields_]

@@ -98,7 +98,7 @@ void default_opts(lpdec::Opts &o)
     o.malp_mode = 0;
     o.malp_max = 200;
     o.ipm_max = 100;
-    o.pcg_maxit = 500;
+    o.pcg_maxit = 0;
     o.ref_max = 3;
     o.precond = 1;
     o.direct = 1;
@@ -124,13 +124,11 @@ lpdec::CodeView view(const lpdec_code *c)
 
 int auto_block(const lpdec_code *c)
 {
-    // the triangular solves and Algorithm 7 run level by level / step by step with little
-    // work per step, so one wave per frame for codes up to a few thousand columns; wider
-    // blocks only for long codes, whose column passes dominate
+    // one wave per frame for tiny codes, whose level sweeps have little work per level;
+    // otherwise four: the column passes and the dense fallback's tile updates spread over
+    // the waves, which outweighs the barriers between levels
     const int q = c->n + c->m;
-    if (q <= 3200) return 64;
-    if (q <= 8000) return 128;
-    return 256;
+    return q <= 600 ? 64 : 256;
 }
 
 // Fills the launch geometry and workspace of Args; launches one workgroup per frame.
@@ -221,7 +219,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_SIGMA: if (!(v > 0 && v < 1)) break; o.sigma = v; return LPDEC_OK;
     case LPDEC_OPT_ETA: if (!(v > 0 && v < 1)) break; o.eta = v; return LPDEC_OK;
     case LPDEC_OPT_PCG_TOL: if (!(v > 0 && v < 1)) break; o.pcg_tol = v; return LPDEC_OK;
-    case LPDEC_OPT_PCG_MAXIT: if (!ipos(1)) break; o.pcg_maxit = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_PCG_MAXIT: if (!ipos(0)) break; o.pcg_maxit = (int)v; return LPDEC_OK;
     case LPDEC_OPT_REF_TOL: if (!(v > 0 && v < 1)) break; o.ref_tol = v; return LPDEC_OK;
     case LPDEC_OPT_REF_MAX: if (!ipos(0)) break; o.ref_max = (int)v; return LPDEC_OK;
     case LPDEC_OPT_IPM_MAX: if (!ipos(1)) break; o.ipm_max = (int)v; return LPDEC_OK;

@@ -56,7 +56,7 @@ struct Plan {
     size_t y, dy, rb, w, b, rho, f64;          // [m]
     size_t c64;                                // 8 x [m]: FP64 PCG vectors (escalation), dy copy
     size_t st64;                               // [m + (n+m) + 1]: s | t of the escalated PCG
-    size_t ridx, colk, dense;                  // dense fallback: i32 [m+1], FP64 [m], FP64 [m*m]
+    size_t ridx, colk, dense;                  // dense fallback: i32 [m+1], FP64 [mp], FP64 [mp*mp], mp = m rounded up to kDenseTile
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
     size_t cold_bytes;
@@ -64,9 +64,10 @@ struct Plan {
 
 __host__ __device__ inline size_t lp_align(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// LDS tiles of the dense fallback: the diagonal block and two panel tiles, 32 x 32 FP64 each
+// LDS of the dense fallback: the factor of the current diagonal tile (32 x 32 FP64), the
+// reciprocals of its diagonal and one block of the substitution vector
 constexpr int kDenseTile = 32;
-constexpr size_t kDenseLdsBytes = 3 * kDenseTile * kDenseTile * 8;
+constexpr size_t kDenseLdsBytes = (kDenseTile * kDenseTile + 2 * kDenseTile) * 8;
 
 __host__ __device__ inline int lp_pow2_at_least(int v, int lo)
 {
@@ -132,8 +133,10 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.st64 = o; o = lp_align(o + 8 * (M + Q + 1));
     p.dense_on = dense ? 1 : 0;
     p.ridx = o; o = lp_align(o + 4 * (M + 1));
-    p.colk = o; o = lp_align(o + 8 * M);
-    p.dense = o; o = lp_align(o + (dense ? 8 * M * M : 0));
+    // the dense system is padded to a whole number of kDenseTile rows
+    const size_t MP = (M + kDenseTile - 1) / kDenseTile * kDenseTile;
+    p.colk = o; o = lp_align(o + 8 * MP);
+    p.dense = o; o = lp_align(o + (dense ? 8 * MP * MP : 0));
     p.u = o; o = lp_align(o + 8 * N);
     p.g = o; o = lp_align(o + 8 * N);
     p.active = o; o = lp_align(o + M);

@@ -78,6 +78,17 @@ LPD_INLINE double dpp_mov(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+
+// The value of a double in one lane (a wave-uniform lane index), for every lane.
+LPD_INLINE double lp_readlane_d(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Accumulator of the FP64 16x16x4 matrix-core product
+typedef double lp_d4 __attribute__((ext_vector_type(4)));
 template <int CTRL>
 LPD_INLINE float dpp_mov(float v)
 {
@@ -428,7 +439,7 @@ struct Frame {
     double *st64;     // s | t | 0 of the escalated FP64 PCG
     int *ridx;        // dense fallback: LP row index of each check
     double *colk, *qd;   // dense fallback: work vector, the p x p matrix (null when absent)
-    double *ldsd;        // dense fallback: three kDenseTile^2 tiles in LDS (set by the kernel)
+    double *ldsd;        // dense fallback: factor of the diagonal tile, reciprocals, vector block (LDS)
     uint8_t *active;
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
@@ -976,7 +987,6 @@ struct Frame {
             }
             __syncthreads();
             // f = A_M^-1 (A_N t) over s; l = h + D_M^-1 f
-            T hl = 0;
             struct HI { T h, i; };
             gsweep<GB, T>(
                 bins, boff, nlb,
@@ -993,11 +1003,14 @@ struct Frame {
                         const int j = b_idx(e);
                         const T fj = b_neg(e) ? -sum : sum;
                         S[j] = fj;
-                        const T lj = hi.h + fj * hi.i;
-                        V.l[j] = lj;
-                        hl += hi.h * lj;
+                        V.l[j] = hi.h + fj * hi.i;
                     }
                 });
+            // h^T l in row order: the rows' slots within a level are placed by atomics, so a
+            // sum taken in the sweep would depend on that placement
+            T hl = 0;
+            for (int j = tid; j < m; j += nt)
+                if (cut(j)) hl += V.h[j] * V.l[j];
             hl = block_sum1(hl, sc);
             if (!(hl > (T)0)) break;
             const T alpha = rr / hl;
@@ -1023,6 +1036,18 @@ struct Frame {
         return it;
     }
 
+    // PCG iteration cap of one round. PCG_MAXIT > 0 is used as given; 0 (automatic) bounds a
+    // round by what the dense fallback would cost for this LP when the fallback exists (its
+    // work grows as p^3: about 160 iterations at p = 470), else 500.
+    LPD_INLINE int pcg_cap() const
+    {
+        if (o.pcg_maxit > 0) return o.pcg_maxit;
+        if (!qd) return 500;
+        const double pp = (double)p;
+        const double cap = pp * pp / 7000.0;
+        return cap < 20.0 ? 20 : (cap > 2000.0 ? 2000 : (int)cap);
+    }
+
     // One refinement round in precision T: r = L^-1 rho, PCG, dy += L^-T v (transforms in
     // FP64). Returns the PCG iterations.
     template <typename T>
@@ -1040,7 +1065,7 @@ struct Frame {
         }
         __syncthreads();
         const long long t0 = wall_clock64();
-        const int its = pcg<T>(V, (T)tol, (T)xi_stop, o.pcg_maxit);
+        const int its = pcg<T>(V, (T)tol, (T)xi_stop, pcg_cap());
         ticks_pcg += wall_clock64() - t0;
         fwd_sub<double>(f64, [&](int j) { return (double)V.v[j] / sqrt(d2[pair[j]]); });
         for (int j = tid; j < m; j += nt)
@@ -1152,101 +1177,232 @@ struct Frame {
         return its;
     }
 
-    // Blocked right-looking Cholesky of the P x P lower triangle of Q (row-major, in global
-    // memory), in place. Per block column of width T = kDenseTile: the diagonal block is
-    // factorised in LDS, the panel rows below it are solved against it one row per thread, and
-    // the trailing lower triangle is updated tile by tile from two panel tiles staged in LDS.
-    // The pivot rule: a pivot not above 1e-30 dm becomes 1e128.
-    LPD_INLINE void chol_blocked(double *Q, int P, double dm)
+    // ------------------------------------------------------------ dense fallback
+    // The Newton matrix Q = A D^2 A^T over the LP rows (ascending check order) is padded to
+    // Pp rows, a multiple of T = kDenseTile, with unit diagonal entries, and held row-major in
+    // the frame's global workspace; only tiles on and below the diagonal are used (diagonal
+    // tiles are read below their diagonal only). Blocked right-looking Cholesky: per block
+    // column K, wave 0 factorises the diagonal tile in registers, every thread solves panel
+    // rows against it, and the waves update the trailing lower tiles on the matrix cores.
+    // Pivot rule: a pivot not above 1e-30 dm becomes 1e128.
+
+    // Diagonal tile at (K, K), wave 0 only: lane r (< T) holds row r and takes the pivots
+    // and the multipliers of the other rows from their lanes. Writes the factor back, and to
+    // LDS column-major (ldsd[c T + r] = L[r][c]) with the reciprocals of its diagonal.
+    LPD_INLINE void dense_diag(double *Q, int Pp, int K, double dm)
     {
         constexpr int T = kDenseTile;
-        double *const D = ldsd, *const PA = ldsd + T * T, *const PB = ldsd + 2 * T * T;
-        for (int K = 0; K < P; K += T) {
-            const int kb = min(T, P - K);
-            for (int t = tid; t < T * T; t += nt) {
-                const int r = t / T, c = t - r * T;
-                D[t] = (r < kb && c <= r) ? Q[(size_t)(K + r) * P + K + c] : 0.0;
+        const int lane = tid & 63, r = lane & (T - 1);
+        double *const row = Q + (size_t)(K + r) * Pp + K;
+        double a[T];
+#pragma unroll
+        for (int c = 0; c < T; c += 2) {
+            const double2 v = *(const double2 *)(row + c);
+            a[c] = lane < T ? v.x : 0.0;
+            a[c + 1] = lane < T ? v.y : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+            double s = lp_readlane_d(a[c], c);
+            if (!(s > 1e-30 * dm)) s = 1e128;
+            const double lcc = sqrt(s), inv = 1.0 / lcc;
+            a[c] = lane == c ? lcc : (lane > c ? a[c] * inv : a[c]);
+            if (lane == 0) ldsd[T * T + c] = inv;
+#pragma unroll
+            for (int cc = c + 1; cc < T; ++cc) a[cc] -= a[c] * lp_readlane_d(a[c], cc);
+        }
+        if (lane < T) {
+#pragma unroll
+            for (int c = 0; c < T; c += 2) *(double2 *)(row + c) = make_double2(a[c], a[c + 1]);
+#pragma unroll
+            for (int c = 0; c < T; ++c) ldsd[c * T + r] = a[c];
+        }
+    }
+
+    // Rows below the diagonal tile: row i becomes x with x L_KK^T = a_i, one thread per row,
+    // the row in registers; each solved entry is subtracted from the later ones at once.
+    LPD_INLINE void dense_panel(double *Q, int Pp, int K)
+    {
+        constexpr int T = kDenseTile;
+        const double *const Lc = ldsd, *const dinv = ldsd + T * T;
+        for (int i = K + T + tid; i < Pp; i += nt) {
+            double *const row = Q + (size_t)i * Pp + K;
+            // an opaque zero offset keeps the factor's LDS reads inside the loop (hoisted
+            // out, they would need 528 registers)
+            int o0 = 0;
+            asm volatile("" : "+v"(o0));
+            double a[T];
+#pragma unroll
+            for (int c = 0; c < T; c += 2) {
+                const double2 v = *(const double2 *)(row + c);
+                a[c] = v.x;
+                a[c + 1] = v.y;
             }
-            __syncthreads();
-            for (int c = 0; c < kb; ++c) {
-                if (tid == 0) {
-                    double s = D[c * T + c];
-                    if (!(s > 1e-30 * dm)) s = 1e128;
-                    D[c * T + c] = sqrt(s);
-                }
-                __syncthreads();
-                const double lcc = D[c * T + c];
-                for (int r = c + 1 + tid; r < kb; r += nt) D[r * T + c] /= lcc;
-                __syncthreads();
-                const int w = kb - c - 1;
-                for (int t = tid; t < w * w; t += nt) {
-                    const int rr = c + 1 + t / w, cc = c + 1 + t % w;
-                    if (cc <= rr) D[rr * T + cc] -= D[rr * T + c] * D[cc * T + c];
-                }
-                __syncthreads();
+#pragma unroll
+            for (int c = 0; c < T; ++c) {
+                a[c] *= dinv[o0 + c];
+#pragma unroll
+                for (int cc = c + 1; cc < T; ++cc) a[cc] -= a[c] * Lc[o0 + c * T + cc];
             }
-            for (int t = tid; t < kb * kb; t += nt) {
-                const int r = t / kb, c = t - r * kb;
-                if (c <= r) Q[(size_t)(K + r) * P + K + c] = D[r * T + c];
-            }
-            // panel: row i solves x L_KK^T = a
-            for (int i = K + kb + tid; i < P; i += nt) {
-                double *const Qi = Q + (size_t)i * P + K;
-                for (int c = 0; c < kb; ++c) {
-                    double v = Qi[c];
-                    for (int t = 0; t < c; ++t) v -= Qi[t] * D[c * T + t];
-                    Qi[c] = v / D[c * T + c];
-                }
-            }
-            __syncthreads();
-            // trailing update of rows and columns >= R0: tile row tI keeps its panel tile PA
-            // while the tiles tJ <= tI stream through PB; each thread accumulates 2 x 2 blocks
-            const int R0 = K + kb, nT = (P - R0 + T - 1) / T;
-            for (int tI = 0; tI < nT; ++tI) {
-                const int I0 = R0 + tI * T;
-                for (int t = tid; t < T * T; t += nt) {
-                    const int r = t / T, c = t - r * T;
-                    PA[t] = (c < kb && I0 + r < P) ? Q[(size_t)(I0 + r) * P + K + c] : 0.0;
-                }
-                for (int tJ = 0; tJ <= tI; ++tJ) {
-                    const int J0 = R0 + tJ * T;
-                    for (int t = tid; t < T * T; t += nt) {
-                        const int r = t / T, c = t - r * T;
-                        PB[t] = (c < kb && J0 + r < P) ? Q[(size_t)(J0 + r) * P + K + c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < T; c += 2) *(double2 *)(row + c) = make_double2(a[c], a[c + 1]);
+        }
+    }
+
+    // Trailing update C -= L_I L_J^T of every tile (I, J) on or below the diagonal right of
+    // block column K; wave w takes every nw-th tile. A 32 x 32 tile is 2 x 2 blocks of the
+    // FP64 16x16x4 product: lane l gives row (l mod 16) of a block at k-slot (l div 16) for
+    // both operands and accumulates rows (l div 16) + 4 v, v = 0..3, of column (l mod 16).
+    // k-slot s of step t is panel column 8 s + t, so each lane reads 8 consecutive entries
+    // of a row.
+    LPD_INLINE void dense_trailing(double *Q, int Pp, int K)
+    {
+        constexpr int T = kDenseTile;
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+        const int lr = lane & 15, lk = lane >> 4;
+        const int R0 = K + T, nT = (Pp - R0) / T;
+        int idx = 0;
+        for (int tI = 0; tI < nT; ++tI) {
+            for (int tJ = 0; tJ <= tI; ++tJ, ++idx) {
+                if (idx % nw != wv) continue;
+                const int I0 = R0 + tI * T, J0 = R0 + tJ * T;
+                lp_d4 acc[2][2];
+                double av[2][8], bv[2][8];
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc[si][sj][v] = Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const double *const pa = Q + (size_t)(I0 + 16 * s + lr) * Pp + K + 8 * lk;
+                    const double *const pb = Q + (size_t)(J0 + 16 * s + lr) * Pp + K + 8 * lk;
+#pragma unroll
+                    for (int k = 0; k < 8; k += 2) {
+                        const double2 x = *(const double2 *)(pa + k), y = *(const double2 *)(pb + k);
+                        av[s][k] = -x.x;
+                        av[s][k + 1] = -x.y;
+                        bv[s][k] = y.x;
+                        bv[s][k + 1] = y.y;
                     }
-                    __syncthreads();
-                    for (int b = tid; b < (T / 2) * (T / 2); b += nt) {
-                        const int r = 2 * (b / (T / 2)), c = 2 * (b % (T / 2));
-                        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
-                        for (int k = 0; k < kb; ++k) {
-                            const double x0 = PA[r * T + k], x1 = PA[(r + 1) * T + k];
-                            const double y0 = PB[c * T + k], y1 = PB[(c + 1) * T + k];
-                            a00 += x0 * y0; a01 += x0 * y1; a10 += x1 * y0; a11 += x1 * y1;
-                        }
-                        const int gi = I0 + r, gj = J0 + c;
-                        if (gi < P && gj <= gi) Q[(size_t)gi * P + gj] -= a00;
-                        if (gi < P && gj + 1 <= gi) Q[(size_t)gi * P + gj + 1] -= a01;
-                        if (gi + 1 < P && gj <= gi + 1) Q[(size_t)(gi + 1) * P + gj] -= a10;
-                        if (gi + 1 < P && gj + 1 <= gi + 1) Q[(size_t)(gi + 1) * P + gj + 1] -= a11;
-                    }
-                    __syncthreads();
                 }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int si = 0; si < 2; ++si)
+#pragma unroll
+                        for (int sj = 0; sj < 2; ++sj)
+                            acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[si][k], bv[sj][k], acc[si][sj], 0, 0, 0);
+#pragma unroll
+                for (int si = 0; si < 2; ++si)
+#pragma unroll
+                    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr] = acc[si][sj][v];
             }
         }
     }
 
-    // Dense fallback for a Newton system the PCG rounds did not finish: Q = A D^2 A^T over the
-    // LP rows (ascending check order) assembled in the frame's global workspace, factorised
-    // in place by Cholesky (lower triangle, row-major; a pivot that is not above 1e-30 of the
-    // largest diagonal entry becomes 1e128, which sets its component to about zero), then
-    // forward and back substitution. Writes dy; the caller recomputes the FP64 residual.
-    LPD_INLINE void direct_solve()
+    // Cholesky factor of the padded Q in place (lower triangle), block column by block column.
+    LPD_INLINE void dense_factor(double *Q, int Pp, double dm)
     {
+        constexpr int T = kDenseTile;
+        for (int K = 0; K < Pp; K += T) {
+            if (tid < 64) dense_diag(Q, Pp, K, dm);
+            __syncthreads();
+            dense_panel(Q, Pp, K);
+            __syncthreads();
+            dense_trailing(Q, Pp, K);
+            __syncthreads();
+        }
+    }
+
+    // L y = colk, then L^T x = y, in place in colk (Pp entries) by blocks of T rows: wave 0
+    // solves the diagonal block in registers, the workgroup updates the other rows.
+    LPD_INLINE void dense_subst(const double *Q, int Pp)
+    {
+        constexpr int T = kDenseTile;
+        double *const xs = ldsd + T * T + T;
+        for (int K = 0; K < Pp; K += T) {
+            if (tid < 64) {
+                const int lane = tid, r = lane & (T - 1);
+                const double *const row = Q + (size_t)(K + r) * Pp + K;
+                double a[T];
+#pragma unroll
+                for (int c = 0; c < T; c += 2) {
+                    const double2 v = *(const double2 *)(row + c);
+                    a[c] = v.x;
+                    a[c + 1] = v.y;
+                }
+                double v = colk[K + r];
+#pragma unroll
+                for (int c = 0; c < T; ++c) {
+                    const double xc = lp_readlane_d(v, c) / lp_readlane_d(a[c], c);
+                    v = lane == c ? xc : (lane > c ? v - a[c] * xc : v);
+                }
+                if (lane < T) { colk[K + r] = v; xs[r] = v; }
+            }
+            __syncthreads();
+            for (int i = K + T + tid; i < Pp; i += nt) {
+                const double *const row = Q + (size_t)i * Pp + K;
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < T; c += 2) {
+                    const double2 v = *(const double2 *)(row + c);
+                    s0 += v.x * xs[c];
+                    s1 += v.y * xs[c + 1];
+                }
+                colk[i] -= s0 + s1;
+            }
+            __syncthreads();
+        }
+        for (int K = Pp - T; K >= 0; K -= T) {
+            if (tid < 64) {
+                const int lane = tid, r = lane & (T - 1);
+                double bc[T];   // bc[c] = L[K + c][K + r]
+#pragma unroll
+                for (int c = 0; c < T; ++c) bc[c] = Q[(size_t)(K + c) * Pp + K + r];
+                double v = colk[K + r];
+#pragma unroll
+                for (int c = T - 1; c >= 0; --c) {
+                    const double xc = lp_readlane_d(v, c) / lp_readlane_d(bc[c], c);
+                    v = lane == c ? xc : (lane < c ? v - bc[c] * xc : v);
+                }
+                if (lane < T) { colk[K + r] = v; xs[r] = v; }
+            }
+            __syncthreads();
+            for (int j = tid; j < K; j += nt) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < T; c += 2) {
+                    s0 += Q[(size_t)(K + c) * Pp + j] * xs[c];
+                    s1 += Q[(size_t)(K + c + 1) * Pp + j] * xs[c + 1];
+                }
+                colk[j] -= s0 + s1;
+            }
+            __syncthreads();
+        }
+    }
+
+    // Dense fallback for a Newton system the PCG rounds did not finish: assembles Q, factorises
+    // it, then forward and back substitution by blocks of T rows (wave 0 solves the diagonal
+    // block in registers, the workgroup updates the rest). Writes dy; the caller recomputes
+    // the FP64 residual. Returns the padded order Pp.
+    LPD_INLINE int direct_solve()
+    {
+        constexpr int T = kDenseTile;
         for (int j = tid; j < m; j += nt) ridx[j] = cut(j) ? 1 : 0;
         block_exscan(ridx, m);
-        const int P = ridx[m];
+        const int P = ridx[m], Pp = (P + T - 1) / T * T;
         double *const Q = qd;
-        for (size_t t = tid; t < (size_t)P * P; t += nt) Q[t] = 0.0;
+        {
+            double2 *const q2 = (double2 *)Q;
+            const size_t n2 = (size_t)Pp * Pp / 2;
+            for (size_t t2 = tid; t2 < n2; t2 += nt) q2[t2] = make_double2(0.0, 0.0);
+        }
         __syncthreads();
         // lower triangle, one thread per LP row: row r gets a_ri a_r'i d_i^2 for every column i
         // of the row and every row r' <= r of that column, and the row's slack weight
@@ -1254,7 +1410,7 @@ struct Frame {
         for (int j = tid; j < m; j += nt) {
             if (!cut(j)) continue;
             const int r = ridx[j];
-            double *const Qr = Q + (size_t)r * P;
+            double *const Qr = Q + (size_t)r * Pp;
             double diag = d2[n + j];
             for (int k = 0; k < RW; ++k) {
                 const uint16_t e = rlist[(size_t)j * RW + k];
@@ -1273,29 +1429,19 @@ struct Frame {
             Qr[r] = diag;
             dm = fmax(dm, diag);
         }
+        for (int r = P + tid; r < Pp; r += nt) Q[(size_t)r * Pp + r] = 1.0;
         dm = block_max_d(dm, sc);
-        chol_blocked(Q, P, dm);
-        // L y = w, then L^T x = y (in colk, indexed by LP row)
+        dense_factor(Q, Pp, dm);
+        // L y = w, then L^T x = y, in colk (indexed by LP row; the padding rows are zero)
         for (int j = tid; j < m; j += nt)
             if (cut(j)) colk[ridx[j]] = w[j];
+        for (int r = P + tid; r < Pp; r += nt) colk[r] = 0.0;
         __syncthreads();
-        for (int c = 0; c < P; ++c) {
-            const double yc = colk[c] / Q[(size_t)c * P + c];
-            __syncthreads();
-            if (tid == 0) colk[c] = yc;
-            for (int r = c + 1 + tid; r < P; r += nt) colk[r] -= Q[(size_t)r * P + c] * yc;
-            __syncthreads();
-        }
-        for (int c = P - 1; c >= 0; --c) {
-            const double xc = colk[c] / Q[(size_t)c * P + c];
-            __syncthreads();
-            if (tid == 0) colk[c] = xc;
-            for (int r = tid; r < c; r += nt) colk[r] -= Q[(size_t)c * P + r] * xc;
-            __syncthreads();
-        }
+        dense_subst(Q, Pp);
         for (int j = tid; j < m; j += nt)
             if (cut(j)) dy[j] = colk[ridx[j]];
         __syncthreads();
+        return Pp;
     }
 
     LPD_INLINE void set_d2f(int c, double dd)
@@ -1413,10 +1559,13 @@ struct Frame {
                 // PCG did not reach the goal (now or earlier in this LP): the Newton system is
                 // solved directly; its residual is at rounding level, so the completion below
                 // gets no correction term
-                direct_solve();
+                const long long td = wall_clock64();
+                const long long pp = direct_solve();
                 for (int j = tid; j < m; j += nt) f64[j] = 0.0;
                 __syncthreads();
                 ++st.direct_solves;
+                st.ticks_dense += wall_clock64() - td;
+                st.dense_cube += pp * pp * pp;
                 direct_mode = true;
             }
             const long long t2 = wall_clock64();

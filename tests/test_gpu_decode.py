@@ -206,22 +206,26 @@ def test_config2_n1024_full_batch(ctx, orc):
     print("decisions on a flat optimal face:", flat)
 
 
-def test_dense_fallback_path(ctx, orc):
+@pytest.mark.parametrize("block", [64, 256])
+def test_dense_fallback_path(ctx, orc, block):
     """With a PCG budget of 2 iterations every Newton solve misses its goal, so every LP after
     its first Newton step runs on the dense Cholesky fallback: that path alone must decode
-    like the oracle."""
+    like the oracle. n=256 gives LPs of up to ~128 rows (several 32-row tiles and a ragged
+    last one); one wave per frame, and four waves sharing the trailing tile updates."""
     import torch
     code = regular_code(256)
     C = _code(ctx, code)
     G = batch_awgn(code.n, 0.5, 1.5, 24, stream=9)
     ctx.set_option("PCG_MAXIT", 2)
     ctx.set_option("REF_MAX", 0)
+    ctx.set_option("BLOCK", block)
     try:
         out = ctx.decode_batch(C, cuda(G, torch.float64))
         torch.cuda.synchronize()
     finally:
-        ctx.set_option("PCG_MAXIT", 500)
+        ctx.set_option("PCG_MAXIT", 0)
         ctx.set_option("REF_MAX", 3)
+        ctx.set_option("BLOCK", 0)
     st = host(out["stats"])
     from paper_0902_0657_amd import stats_table
     s = stats_table(st)

@@ -38,14 +38,10 @@ def _case(name):
     return code, G, g["frames"]
 
 
-CASES = [("n4096_awgn_1.75dB", 0), ("n4096_awgn_1.75dB", 1), ("n4096_awgn_1.75dB", 3),
-         pytest.param("n4096_awgn_1.75dB", 2, marks=pytest.mark.xfail(
-             reason="fractional n=4096 frame: from its 7th LP on PCG misses the inexact-Newton goal on the "
-                    "late systems; with the dense Cholesky fallback the decode needs ~300 dense solves at "
-                    "p ~ 1800 (about 0.15-0.3 s each) and outlasts this test's budget, without it the IPM "
-                    "reaches its iteration cap (flag -1); the test runs without the fallback so it fails fast",
-             strict=False)),
-         ("n8192_irregular_bsc_0.04", 0), ("n8192_irregular_bsc_0.04", 1)]
+# frame 2 is fractional: from its 7th LP on PCG misses the inexact-Newton goal on the late
+# systems and the dense fallback finishes them (~580 dense solves at p up to ~1850, about 30 s)
+CASES = [("n4096_awgn_1.75dB", 0), ("n4096_awgn_1.75dB", 1), ("n4096_awgn_1.75dB", 2),
+         ("n4096_awgn_1.75dB", 3), ("n8192_irregular_bsc_0.04", 0), ("n8192_irregular_bsc_0.04", 1)]
 
 
 @pytest.mark.parametrize("name,k", CASES)
@@ -55,14 +51,8 @@ def test_large_code_golden_frame(ctx, name, k):
     code, G, frames = _case(name)
     C = Code.from_synth(ctx, code)
     g = G[k:k + 1]
-    slow = name == "n4096_awgn_1.75dB" and k == 2
-    if slow:
-        ctx.set_option("DIRECT_FALLBACK", 0)
-    try:
-        out = ctx.decode_batch(C, cuda(g, torch.float64), want_u=True)
-        torch.cuda.synchronize()
-    finally:
-        ctx.set_option("DIRECT_FALLBACK", 1)
+    out = ctx.decode_batch(C, cuda(g, torch.float64), want_u=True)
+    torch.cuda.synchronize()
     xh, fl, ob, u, st = host(out["xhat"])[0], host(out["flag"])[0], host(out["obj"])[0], host(out["u"])[0], host(out["stats"])[0]
     gr = frames[str(k)]
     want = np.unpackbits(np.frombuffer(bytes.fromhex(gr["xhat_hex"]), np.uint8))[:code.n]
