@@ -1186,30 +1186,37 @@ struct Frame {
     // rows against it, and the waves update the trailing lower tiles on the matrix cores.
     // Pivot rule: a pivot not above 1e-30 dm becomes 1e128.
 
-    // Diagonal tile at (K, K), wave 0 only: lane r (< T) holds row r and takes the pivots
-    // and the multipliers of the other rows from their lanes. Writes the factor back, and to
-    // LDS column-major (ldsd[c T + r] = L[r][c]) with the reciprocals of its diagonal.
+    // Diagonal tile at (K, K), wave 0 only: lanes r and r + 32 both hold row r in registers
+    // and compute the same values, so every LDS store of the loop is unconditional (equal
+    // values to one address). Per pivot column c the lanes post their entry of the column to
+    // LDS and read the pivot and the multipliers of the later rows back as broadcasts. Writes the factor back to Q with the
+    // reciprocal of each diagonal entry in place of the entry (what the substitutions use),
+    // and to LDS column-major (ldsd[c T + r] = L[r][c], c < r) with the reciprocals at
+    // ldsd[T T + c].
     LPD_INLINE void dense_diag(double *Q, int Pp, int K, double dm)
     {
         constexpr int T = kDenseTile;
         const int lane = tid & 63, r = lane & (T - 1);
         double *const row = Q + (size_t)(K + r) * Pp + K;
+        double *const colbuf = ldsd;   // column c of the tile before scaling, at colbuf[c T + r]
         double a[T];
 #pragma unroll
         for (int c = 0; c < T; c += 2) {
             const double2 v = *(const double2 *)(row + c);
-            a[c] = lane < T ? v.x : 0.0;
-            a[c + 1] = lane < T ? v.y : 0.0;
+            a[c] = v.x;
+            a[c + 1] = v.y;
         }
 #pragma unroll
         for (int c = 0; c < T; ++c) {
-            double s = lp_readlane_d(a[c], c);
+            colbuf[c * T + r] = a[c];
+            double s = colbuf[c * T + c];
             if (!(s > 1e-30 * dm)) s = 1e128;
             const double lcc = sqrt(s), inv = 1.0 / lcc;
-            a[c] = lane == c ? lcc : (lane > c ? a[c] * inv : a[c]);
-            if (lane == 0) ldsd[T * T + c] = inv;
+            a[c] = r == c ? inv : (r > c ? a[c] * inv : a[c]);
+            ldsd[T * T + c] = inv;
+            const double lrc = a[c];
 #pragma unroll
-            for (int cc = c + 1; cc < T; ++cc) a[cc] -= a[c] * lp_readlane_d(a[c], cc);
+            for (int cc = c + 1; cc < T; ++cc) a[cc] -= lrc * (colbuf[c * T + cc] * inv);
         }
         if (lane < T) {
 #pragma unroll
@@ -1250,58 +1257,84 @@ struct Frame {
     }
 
     // Trailing update C -= L_I L_J^T of every tile (I, J) on or below the diagonal right of
-    // block column K; wave w takes every nw-th tile. A 32 x 32 tile is 2 x 2 blocks of the
-    // FP64 16x16x4 product: lane l gives row (l mod 16) of a block at k-slot (l div 16) for
-    // both operands and accumulates rows (l div 16) + 4 v, v = 0..3, of column (l mod 16).
-    // k-slot s of step t is panel column 8 s + t, so each lane reads 8 consecutive entries
-    // of a row.
+    // block column K. A 32 x 32 tile is 2 x 2 blocks of the FP64 16x16x4 matrix-core product:
+    // lane l gives row (l mod 16) of a block at k-slot (l div 16) for both operands and
+    // accumulates rows (l div 16) + 4 v, v = 0..3, of column (l mod 16). k-slot s of step t
+    // is panel column 8 s + t, so each lane reads 8 consecutive entries of a row. A wave owns
+    // whole tile rows (longest first, dealt in zig-zag order over the waves), keeps the row's
+    // panel operand in registers and loads the next tile while the current one is computed.
+    struct DTile {
+        lp_d4 acc[2][2];
+        double bv[2][8];
+    };
+    LPD_INLINE void dtile_load(const double *Q, int Pp, int K, int I0, int J0, int lr, int lk, DTile &t)
+    {
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    t.acc[si][sj][v] = Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double *const pb = Q + (size_t)(J0 + 16 * s + lr) * Pp + K + 8 * lk;
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                const double2 y = *(const double2 *)(pb + k);
+                t.bv[s][k] = y.x;
+                t.bv[s][k + 1] = y.y;
+            }
+        }
+    }
+    LPD_INLINE void dtile_finish(double *Q, int Pp, int I0, int J0, int lr, int lk, DTile &t,
+                                 const double (&av)[2][8])
+    {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int si = 0; si < 2; ++si)
+#pragma unroll
+                for (int sj = 0; sj < 2; ++sj)
+                    t.acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[si][k], t.bv[sj][k], t.acc[si][sj], 0, 0, 0);
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+            for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr] = t.acc[si][sj][v];
+    }
     LPD_INLINE void dense_trailing(double *Q, int Pp, int K)
     {
         constexpr int T = kDenseTile;
         const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
         const int lr = lane & 15, lk = lane >> 4;
         const int R0 = K + T, nT = (Pp - R0) / T;
-        int idx = 0;
-        for (int tI = 0; tI < nT; ++tI) {
-            for (int tJ = 0; tJ <= tI; ++tJ, ++idx) {
-                if (idx % nw != wv) continue;
-                const int I0 = R0 + tI * T, J0 = R0 + tJ * T;
-                lp_d4 acc[2][2];
-                double av[2][8], bv[2][8];
+        for (int k = 0; k < nT; ++k) {
+            const int z = k % (2 * nw);
+            if ((z < nw ? z : 2 * nw - 1 - z) != wv) continue;
+            const int tI = nT - 1 - k, I0 = R0 + tI * T;
+            double av[2][8];
 #pragma unroll
-                for (int si = 0; si < 2; ++si)
+            for (int s = 0; s < 2; ++s) {
+                const double *const pa = Q + (size_t)(I0 + 16 * s + lr) * Pp + K + 8 * lk;
 #pragma unroll
-                    for (int sj = 0; sj < 2; ++sj)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            acc[si][sj][v] = Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const double *const pa = Q + (size_t)(I0 + 16 * s + lr) * Pp + K + 8 * lk;
-                    const double *const pb = Q + (size_t)(J0 + 16 * s + lr) * Pp + K + 8 * lk;
-#pragma unroll
-                    for (int k = 0; k < 8; k += 2) {
-                        const double2 x = *(const double2 *)(pa + k), y = *(const double2 *)(pb + k);
-                        av[s][k] = -x.x;
-                        av[s][k + 1] = -x.y;
-                        bv[s][k] = y.x;
-                        bv[s][k + 1] = y.y;
-                    }
+                for (int kk = 0; kk < 8; kk += 2) {
+                    const double2 x = *(const double2 *)(pa + kk);
+                    av[s][kk] = -x.x;
+                    av[s][kk + 1] = -x.y;
                 }
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-#pragma unroll
-                    for (int si = 0; si < 2; ++si)
-#pragma unroll
-                        for (int sj = 0; sj < 2; ++sj)
-                            acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[si][k], bv[sj][k], acc[si][sj], 0, 0, 0);
-#pragma unroll
-                for (int si = 0; si < 2; ++si)
-#pragma unroll
-                    for (int sj = 0; sj < 2; ++sj)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            Q[(size_t)(I0 + 16 * si + lk + 4 * v) * Pp + J0 + 16 * sj + lr] = acc[si][sj][v];
+            }
+            DTile t0, t1;
+            dtile_load(Q, Pp, K, I0, R0, lr, lk, t0);
+            for (int tJ = 0;;) {
+                if (tJ + 1 <= tI) dtile_load(Q, Pp, K, I0, R0 + (tJ + 1) * T, lr, lk, t1);
+                dtile_finish(Q, Pp, I0, R0 + tJ * T, lr, lk, t0, av);
+                if (++tJ > tI) break;
+                if (tJ + 1 <= tI) dtile_load(Q, Pp, K, I0, R0 + (tJ + 1) * T, lr, lk, t0);
+                dtile_finish(Q, Pp, I0, R0 + tJ * T, lr, lk, t1, av);
+                if (++tJ > tI) break;
             }
         }
     }
@@ -1321,7 +1354,8 @@ struct Frame {
     }
 
     // L y = colk, then L^T x = y, in place in colk (Pp entries) by blocks of T rows: wave 0
-    // solves the diagonal block in registers, the workgroup updates the other rows.
+    // solves the diagonal block in registers, the workgroup updates the other rows. The
+    // diagonal of Q holds the reciprocals of L's diagonal.
     LPD_INLINE void dense_subst(const double *Q, int Pp)
     {
         constexpr int T = kDenseTile;
@@ -1340,7 +1374,7 @@ struct Frame {
                 double v = colk[K + r];
 #pragma unroll
                 for (int c = 0; c < T; ++c) {
-                    const double xc = lp_readlane_d(v, c) / lp_readlane_d(a[c], c);
+                    const double xc = lp_readlane_d(v, c) * lp_readlane_d(a[c], c);
                     v = lane == c ? xc : (lane > c ? v - a[c] * xc : v);
                 }
                 if (lane < T) { colk[K + r] = v; xs[r] = v; }
@@ -1368,7 +1402,7 @@ struct Frame {
                 double v = colk[K + r];
 #pragma unroll
                 for (int c = T - 1; c >= 0; --c) {
-                    const double xc = lp_readlane_d(v, c) / lp_readlane_d(bc[c], c);
+                    const double xc = lp_readlane_d(v, c) * lp_readlane_d(bc[c], c);
                     v = lane == c ? xc : (lane < c ? v - bc[c] * xc : v);
                 }
                 if (lane < T) { colk[K + r] = v; xs[r] = v; }
