@@ -116,18 +116,25 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
  *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
  *                  XI_TOL goal is solved again by a dense Cholesky factorisation of
- *                  A D^2 A^T on the GPU (FP64, in the frame's global workspace, 8 m^2 bytes
- *                  per frame); 0 = keep the PCG result
+ *                  A D^2 A^T on the GPU (FP64 matrix cores, in the frame's global workspace,
+ *                  8 mp^2 bytes per frame, mp = m rounded up to 32), and so are the LP's
+ *                  later Newton systems; 0 = keep the PCG result
  *   IPM_STALL      once the largest of the three IPM error measures is below IPM_STALL but
  *                  has not at least halved over the last two iterations, the LP counts as
  *                  solved (the double-precision floor of a degenerate LP) (1e-7)
+ *   MTS_REUSE      R >= 1: the preconditioning set is searched on IPM iterations 0, R, 2R, ...
+ *                  of each LP and kept in between (1 = every iteration, Sec. V-B; default)
+ *   WARM_START     1 = from the second IPM iteration of an LP on, a Newton solve starts from
+ *                  the previous direction dy when that leaves a smaller residual than 0
+ *                  (Algorithm 4's initial guess); 0 (default) = starts from 0
  */
 enum {
     LPDEC_OPT_MALP_MODE = 0, LPDEC_OPT_PRECISION, LPDEC_OPT_TAU_VIOL, LPDEC_OPT_TAU_ACT,
     LPDEC_OPT_TAU_INT, LPDEC_OPT_IPM_EPS, LPDEC_OPT_SIGMA, LPDEC_OPT_ETA, LPDEC_OPT_PCG_TOL,
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
-    LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT__COUNT
+    LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT_MTS_REUSE, LPDEC_OPT_WARM_START,
+    LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);

@@ -16,6 +16,8 @@ struct Opts {
     int ref_max;
     int precond;     // 1: triangular preconditioner, 0: M = I
     int direct;      // 1: dense Cholesky fallback for Newton solves PCG does not finish
+    int mts_reuse;   // the triangular set is searched on every mts_reuse-th IPM iteration of an LP
+    int warm;        // 1: a Newton solve starts from the previous direction of the same LP
     double tau_viol, tau_act, tau_int;
     double eps, eps_stall, sigma, eta;
     double pcg_tol, ref_tol, xi_tol;

@@ -1118,15 +1118,16 @@ struct Frame {
     // Returns PCG iterations; refine_rounds counts the extra rounds, escal the switches;
     // resid2 = ||rho||^2 / ||w||^2. On return rho holds the final residual and, when mu > 0,
     // f64 holds A_M^-1 rho.
-    LPD_INLINE int solve(double mu, int &refine_rounds, int &escal, double &resid2, bool &met)
+    LPD_INLINE int solve(double mu, int &refine_rounds, int &escal, double &resid2, bool &met, bool warm = false)
     {
         met = true;
         double nw2 = 0.0;
         for (int j = tid; j < m; j += nt) {
             const double wj = cut(j) ? w[j] : 0.0;
+            const double d0 = warm && cut(j) ? dy[j] : 0.0;
             rho[j] = wj;
-            dy[j] = 0.0;
-            c64[7][j] = 0.0;
+            dy[j] = d0;
+            c64[7][j] = d0;
             nw2 += wj * wj;
         }
         nw2 = block_sum1(nw2, sc);
@@ -1135,6 +1136,16 @@ struct Frame {
             for (int j = tid; j < m; j += nt) f64[j] = 0.0;
             __syncthreads();
             return 0;
+        }
+        if (warm && !(residual64() < nw2)) {
+            // the previous Newton direction (the initial guess of Algorithm 4) is kept only
+            // when it leaves a smaller residual than 0 does
+            for (int j = tid; j < m; j += nt) {
+                rho[j] = cut(j) ? w[j] : 0.0;
+                dy[j] = 0.0;
+                c64[7][j] = 0.0;
+            }
+            __syncthreads();
         }
         const bool use_xi = mu > 0.0;
         const double xi_goal = o.xi_tol * mu;
@@ -1577,9 +1588,13 @@ struct Frame {
             __syncthreads();
             for (int j = tid; j < m; j += nt)
                 if (cut(j)) w[j] = rb[j] + row_dot<double>(j, tq);
-            // preconditioner for this iteration (Sec. V-B: found anew at every iteration)
+            // preconditioner for this iteration. Sec. V-B searches it anew at every iteration;
+            // with MTS_REUSE = R > 1 the set found on iteration it - (it mod R) of this LP is
+            // kept (the weights d of the current iteration still enter through D_M), which is
+            // the reuse across iterations that Sec. V-C leaves open
             const long long t0 = wall_clock64();
-            if (!direct_mode) {
+            const bool search = it % o.mts_reuse == 0;
+            if (!direct_mode && search) {
                 if (o.precond) mts(nullptr);
                 else slack_basis();
                 build_levels();
@@ -1588,7 +1603,7 @@ struct Frame {
             const long long t1 = wall_clock64();
             double resid2 = 0.0;
             bool met = true;
-            const int pits = direct_mode ? 0 : solve(mu, st.ref_rounds, st.escalations, resid2, met);
+            const int pits = direct_mode ? 0 : solve(mu, st.ref_rounds, st.escalations, resid2, met, o.warm && it > 0);
             if ((direct_mode || !met) && qd) {
                 // PCG did not reach the goal (now or earlier in this LP): the Newton system is
                 // solved directly; its residual is at rounding level, so the completion below
@@ -1605,7 +1620,7 @@ struct Frame {
             const long long t2 = wall_clock64();
             st.ticks_mts += t1 - t0;
             st.ticks_solve += t2 - t1;
-            st.mts_rounds += o.precond && !direct_mode ? p : 0;
+            st.mts_rounds += o.precond && !direct_mode && search ? p : 0;
             st.pcg_iters += pits;
             st.pcg_rows += (long long)pits * p;
             st.ipm_cols += n + p;

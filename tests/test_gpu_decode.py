@@ -169,6 +169,31 @@ def test_edge_cases(ctx, orc):
     assert empty["flag"].numel() == 0
 
 
+@pytest.mark.parametrize("opt,val", [("MTS_REUSE", 2), ("MTS_REUSE", 4), ("WARM_START", 1)])
+def test_preconditioner_reuse_and_warm_start(ctx, orc, opt, val):
+    """The preconditioning set kept over several IPM iterations of an LP (MTS_REUSE), or each
+    Newton solve started from the previous direction (WARM_START): the decode still equals the
+    oracle's; reuse runs fewer triangular-set searches."""
+    import torch
+    from paper_0902_0657_amd import stats_table
+    code = regular_code(256)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 1.5, 24, stream=12)
+    default = ctx.get_option(opt)
+    outs = {}
+    for v in (default, val):
+        ctx.set_option(opt, v)
+        try:
+            outs[v] = ctx.decode_batch(C, cuda(G, torch.float64))
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option(opt, default)
+    _compare(orc, code, G, outs[val])
+    if opt == "MTS_REUSE":
+        s1, sr = stats_table(host(outs[default]["stats"])), stats_table(host(outs[val]["stats"]))
+        assert sr["mts_rounds"].sum() < s1["mts_rounds"].sum()
+
+
 def _n1024_batch():
     """The benchmark's workload: (3,6) n=1024, 171/171/170 frames at Eb/N0 1.5/2.0/2.5 dB,
     FP32 LLRs, one launch of 512 frames."""
