@@ -24,6 +24,11 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# HIP's hardware queues per process (read when HIP starts; HIP's default is 4): the server's 8
+# streams need a queue each, or their waves serialize behind each other, plus one for the
+# other work of this process
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 12:
+    os.environ["GPU_MAX_HW_QUEUES"] = "12"
 
 N, SNRS, SPLIT = 1024, (1.5, 2.0, 2.5), (171, 171, 170)
 HBM_PEAK_GBS = 8000.0
@@ -113,7 +118,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving(ctx, seconds=10.0, qps=None, seed=5, full=False):
+def serving(ctx, seconds=10.0, qps=None, seed=5, full=False, streams=None):
     """Poisson arrivals of frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through
     lpdec_server (continuous batching over four streams). Latency = submit to result, per
     request. Default mix: (3,6) n=256 and n=1024; full: also (3,6) n=4096 and the irregular
@@ -126,6 +131,8 @@ def serving(ctx, seconds=10.0, qps=None, seed=5, full=False):
         codes += [regular_code(4096), irregular_code(8192)]
     Cs = [Code.from_synth(ctx, c) for c in codes]
     rng = np.random.Generator(np.random.PCG64(seed))
+    if streams:
+        ctx.set_option("SERVER_STREAMS", streams)
     srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
     qps = qps or 40.0
     t0 = time.perf_counter()
@@ -150,6 +157,7 @@ def serving(ctx, seconds=10.0, qps=None, seed=5, full=False):
     srv.close()
     lat = np.array(lat)
     return {"codes": [c.name for c in codes], "requests": len(lat), "offered_qps": qps, "arrival_s": seconds,
+            "streams": int(ctx.get_option("SERVER_STREAMS")),
             "frames_per_s": len(lat) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "per_code_p50_ms": {str(n): float(np.percentile(v, 50) * 1e3) for n, v in sorted(per.items())},

@@ -60,6 +60,7 @@ struct lpdec_ctx {
     lpdec::Opts opts{};
     int precision = -1;   // -1: per call default
     int block = 0;        // 0: automatic
+    int server_streams = 8;
     int lds_limit = 65536;
     std::string err;
     Workspace ws;
@@ -231,6 +232,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
         ctx->block = (int)v;
         return LPDEC_OK;
     case LPDEC_OPT_PRECOND: if (v != 0 && v != 1) break; o.precond = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_SERVER_STREAMS: if (!ipos(1) || v > 32) break; ctx->server_streams = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
     case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;
     case LPDEC_OPT_DIRECT_FALLBACK: if (v != 0 && v != 1) break; o.direct = (int)v; return LPDEC_OK;
@@ -262,6 +264,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_MALP_MAX: *v = o.malp_max; break;
     case LPDEC_OPT_BLOCK: *v = ctx->block; break;
     case LPDEC_OPT_PRECOND: *v = o.precond; break;
+    case LPDEC_OPT_SERVER_STREAMS: *v = ctx->server_streams; break;
     case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
     case LPDEC_OPT_IPM_STALL: *v = o.eps_stall; break;
     case LPDEC_OPT_DIRECT_FALLBACK: *v = o.direct; break;
@@ -344,7 +347,8 @@ extern "C" lpdec_status lpdec_code_destroy(lpdec_code *c)
 static lpdec_status decode_batch_impl(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
                                       const void *gamma, int32_t gdt, uint8_t *xhat, int32_t *flag,
                                       double *obj, lpdec_stats *stats, double *u, uint32_t *trace,
-                                      int32_t trace_cap, int pt64, Workspace &ws, hipStream_t stream)
+                                      int32_t trace_cap, int pt64, Workspace &ws, hipStream_t stream,
+                                      int32_t *done = nullptr)
 {
     if (nframes > 0 && (!gamma || !xhat || !flag)) return fail(ctx, LPDEC_EINVAL, "null gamma/xhat/flag");
     if (gdt != 0 && gdt != 1) return fail(ctx, LPDEC_EINVAL, "gamma_dtype must be 0 (f32) or 1 (f64)");
@@ -355,6 +359,7 @@ static lpdec_status decode_batch_impl(lpdec_ctx *ctx, const lpdec_code *code, in
     a.gamma_f64 = gdt;
     a.xhat = xhat; a.flag = flag; a.obj = obj; a.stats = stats; a.u_out = u;
     a.trace = trace; a.trace_cap = trace ? trace_cap : 0;
+    a.done = done;
     return launch(ctx, code, a, pt64, ws, stream);
 }
 
@@ -512,8 +517,10 @@ extern "C" lpdec_status lpdec_ipm_batch(lpdec_ctx *ctx, const lpdec_code *code, 
 // per wave) while the wave's device footprint fits in the free part of the HBM budget and
 // the slots in flight stay under max_slots, copies their gamma to the wave's device buffer,
 // launches the decode kernel on that stream and records an event. Waves on different
-// streams overlap on the device; a finished wave's results are copied back and its memory
-// and slots are released, so frames that arrived meanwhile are admitted.
+// streams overlap on the device. Each frame's results go to host-mapped pinned memory with a
+// done flag that the kernel raises once they are visible, so the scheduler hands a frame's
+// result out as soon as that frame is decoded, not when its wave ends; a wave's memory and
+// slots are released when its kernel ends, and frames that arrived meanwhile are admitted.
 namespace {
 
 struct Request {
@@ -530,12 +537,41 @@ struct Result {
     double latency = 0.0;
 };
 
+// Host-mapped pinned memory (fine-grained): the kernel writes a frame's results and its done
+// flag here, and the server thread reads them while the wave still runs.
+struct HostOut {
+    char *h = nullptr;            // host address
+    char *d = nullptr;            // the same memory as the device addresses it
+    size_t bytes = 0;
+};
+
+hipError_t hostout_ensure(HostOut &o, size_t bytes)
+{
+    if (bytes <= o.bytes) return hipSuccess;
+    if (o.h) {
+        hipError_t e = hipHostFree(o.h);
+        if (e != hipSuccess) return e;
+        o.h = o.d = nullptr;
+        o.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    hipError_t e = hipHostMalloc((void **)&o.h, want, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) { o.h = nullptr; return e; }
+    e = hipHostGetDevicePointer((void **)&o.d, o.h, 0);
+    if (e != hipSuccess) { (void)hipHostFree(o.h); o.h = o.d = nullptr; return e; }
+    o.bytes = want;
+    return hipSuccess;
+}
+
 struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     Workspace ws;                 // kernel workspace of this lane
-    Workspace io;                 // gamma in, results out
+    Workspace io;                 // gamma in
+    HostOut out;                  // xhat | flag | obj | done of every frame of the wave
     std::vector<Request> wave;    // frames in flight on this lane
+    std::vector<char> retired;    // per frame: its result has been taken
+    int nretired = 0;
     size_t footprint = 0;
     bool busy = false;
 };
@@ -571,82 +607,122 @@ size_t frame_footprint(const lpdec_code *c, int pt64)
 
 void server_loop(lpdec_server *s)
 {
+    // Lane state belongs to this thread alone; the mutex guards what the client calls share
+    // (queue, results, pending, budget counters), and no HIP call is made while holding it.
     (void)hipSetDevice(s->ctx->device);
     const int pt64 = precision_for(s->ctx, 1);
-    std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
-        // retire finished waves
-        bool progressed = false;
+        // retire finished frames as their done flags appear, and a lane once its kernel ended
+        std::vector<std::pair<uint64_t, Result>> done;
+        size_t freed_bytes = 0;
+        int freed_slots = 0;
         for (auto &L : s->lanes) {
             if (!L.busy) continue;
-            if (hipEventQuery(L.done) != hipSuccess) continue;
-            const auto now = std::chrono::steady_clock::now();
+            const bool ended = hipEventQuery(L.done) == hipSuccess;
             const int nf = (int)L.wave.size();
             const int n = L.wave[0].code->n;
-            std::vector<uint8_t> xh((size_t)nf * n);
-            std::vector<int32_t> fl(nf);
-            std::vector<double> ob(nf);
-            char *base = L.io.ptr;
-            const size_t off_x = lpdec::lp_align(8 * (size_t)nf * n);
-            const size_t off_f = off_x + lpdec::lp_align((size_t)nf * n);
+            const size_t off_f = lpdec::lp_align((size_t)nf * n);
             const size_t off_o = off_f + lpdec::lp_align(4 * (size_t)nf);
-            hipError_t e = hipMemcpy(xh.data(), base + off_x, xh.size(), hipMemcpyDeviceToHost);
-            if (e == hipSuccess) e = hipMemcpy(fl.data(), base + off_f, 4 * (size_t)nf, hipMemcpyDeviceToHost);
-            if (e == hipSuccess) e = hipMemcpy(ob.data(), base + off_o, 8 * (size_t)nf, hipMemcpyDeviceToHost);
+            const size_t off_d = off_o + lpdec::lp_align(8 * (size_t)nf);
+            const volatile int32_t *dn = (const volatile int32_t *)(L.out.h + off_d);
+            const auto now = std::chrono::steady_clock::now();
             for (int k = 0; k < nf; ++k) {
+                if (L.retired[k] || !(dn[k] || ended)) continue;
+                std::atomic_thread_fence(std::memory_order_acquire);
                 Result r;
-                r.xhat.assign(xh.begin() + (size_t)k * n, xh.begin() + (size_t)(k + 1) * n);
-                r.flag = e == hipSuccess ? fl[k] : LPDEC_FLAG_NONFINITE;
-                r.obj = ob[k];
+                if (dn[k]) {
+                    const uint8_t *xh = (const uint8_t *)L.out.h + (size_t)k * n;
+                    r.xhat.assign(xh, xh + n);
+                    r.flag = ((const volatile int32_t *)(L.out.h + off_f))[k];
+                    r.obj = ((const volatile double *)(L.out.h + off_o))[k];
+                } else {
+                    // the kernel ended without marking this frame
+                    r.xhat.assign(n, 0);
+                    r.flag = LPDEC_FLAG_NONFINITE;
+                }
                 r.latency = std::chrono::duration<double>(now - L.wave[k].t_submit).count();
-                s->results[L.wave[k].ticket] = std::move(r);
-                s->pending.erase(L.wave[k].ticket);
+                done.emplace_back(L.wave[k].ticket, std::move(r));
+                L.retired[k] = 1;
+                ++L.nretired;
             }
-            s->in_use -= L.footprint;
-            s->slots_in_use -= nf;
+            if (!ended) continue;
+            freed_bytes += L.footprint;
+            freed_slots += nf;
             L.wave.clear();
             L.busy = false;
-            progressed = true;
         }
-        if (progressed) s->cv_done.notify_all();
-        // admit a new wave on every idle lane while the queue head fits
-        for (auto &L : s->lanes) {
-            if (L.busy || s->queue.empty()) continue;
-            const lpdec_code *code = s->queue.front().code;
-            const size_t fp = frame_footprint(code, pt64);
-            int nf = 0;
-            size_t need = 0;
-            for (auto it = s->queue.begin(); it != s->queue.end() && it->code == code; ++it) {
-                if (s->slots_in_use + nf + 1 > s->max_slots) break;
-                if (s->in_use + need + fp > s->budget) break;
-                need += fp;
-                ++nf;
+        // admission: take a wave for every idle lane while the queue head fits
+        struct Launch { Lane *L; size_t need; };
+        std::vector<Launch> launches;
+        bool any_busy = false, stop = false;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &d : done) {
+                s->results[d.first] = std::move(d.second);
+                s->pending.erase(d.first);
             }
-            if (nf == 0) break;
-            for (int k = 0; k < nf; ++k) { L.wave.push_back(std::move(s->queue.front())); s->queue.pop_front(); }
+            s->in_use -= freed_bytes;
+            s->slots_in_use -= freed_slots;
+            for (auto &L : s->lanes) {
+                if (L.busy || s->queue.empty()) continue;
+                const lpdec_code *code = s->queue.front().code;
+                const size_t fp = frame_footprint(code, pt64);
+                int nf = 0;
+                size_t need = 0;
+                for (auto it = s->queue.begin(); it != s->queue.end() && it->code == code; ++it) {
+                    if (s->slots_in_use + nf + 1 > s->max_slots) break;
+                    if (s->in_use + need + fp > s->budget) break;
+                    need += fp;
+                    ++nf;
+                }
+                if (nf == 0) break;
+                for (int k = 0; k < nf; ++k) { L.wave.push_back(std::move(s->queue.front())); s->queue.pop_front(); }
+                s->in_use += need;
+                s->slots_in_use += nf;
+                L.busy = true;
+                launches.push_back({&L, need});
+            }
+            stop = s->stop;
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+        for (auto &ln : launches) {
+            Lane &L = *ln.L;
+            const lpdec_code *code = L.wave[0].code;
+            const int nf = (int)L.wave.size();
             const int n = code->n;
-            const size_t off_x = lpdec::lp_align(8 * (size_t)nf * n);
-            const size_t off_f = off_x + lpdec::lp_align((size_t)nf * n);
+            const size_t off_f = lpdec::lp_align((size_t)nf * n);
             const size_t off_o = off_f + lpdec::lp_align(4 * (size_t)nf);
-            const size_t io_bytes = off_o + 8 * (size_t)nf;
+            const size_t off_d = off_o + lpdec::lp_align(8 * (size_t)nf);
+            const size_t out_bytes = off_d + 4 * (size_t)nf;
             std::vector<double> g((size_t)nf * n);
             for (int k = 0; k < nf; ++k) std::copy(L.wave[k].gamma.begin(), L.wave[k].gamma.end(), g.begin() + (size_t)k * n);
-            hipError_t e = ws_ensure(L.io, io_bytes);
-            if (e == hipSuccess) e = hipMemcpyAsync(L.io.ptr, g.data(), 8 * g.size(), hipMemcpyHostToDevice, L.stream);
+            hipError_t e = ws_ensure(L.io, 8 * g.size());
+            if (e == hipSuccess) e = hostout_ensure(L.out, out_bytes);
+            if (e == hipSuccess) {
+                // the lane is idle, so nothing reads the previous wave's flags any more
+                std::memset(L.out.h + off_d, 0, 4 * (size_t)nf);
+                std::atomic_thread_fence(std::memory_order_release);
+                e = hipMemcpyAsync(L.io.ptr, g.data(), 8 * g.size(), hipMemcpyHostToDevice, L.stream);
+            }
+            L.retired.assign(nf, 0);
+            L.nretired = 0;
+            L.footprint = ln.need;
             lpdec_status st = LPDEC_EDEVICE;
             if (e == hipSuccess) {
-                // the stream's previous use of this gamma buffer is over: the copy is ordered
-                // before the kernel on the same stream; synchronise the copy so g can go
+                // the copy is ordered before the kernel on the same stream; synchronise it so
+                // g can go
                 e = hipStreamSynchronize(L.stream);
                 st = e == hipSuccess
-                         ? decode_batch_impl(s->ctx, code, nf, L.io.ptr, 1, (uint8_t *)(L.io.ptr + off_x),
-                                             (int32_t *)(L.io.ptr + off_f), (double *)(L.io.ptr + off_o),
-                                             nullptr, nullptr, nullptr, 0, pt64, L.ws, L.stream)
+                         ? decode_batch_impl(s->ctx, code, nf, L.io.ptr, 1, (uint8_t *)L.out.d,
+                                             (int32_t *)(L.out.d + off_f), (double *)(L.out.d + off_o),
+                                             nullptr, nullptr, nullptr, 0, pt64, L.ws, L.stream,
+                                             (int32_t *)(L.out.d + off_d))
                          : LPDEC_EDEVICE;
             }
             if (st == LPDEC_OK) e = hipEventRecord(L.done, L.stream);
             if (st != LPDEC_OK || e != hipSuccess) {
-                // report the failure on every frame of the wave
+                // report the failure on every frame of the wave and give its budget back
+                std::lock_guard<std::mutex> lk(s->mu);
                 for (auto &r : L.wave) {
                     Result res;
                     res.xhat.assign(n, 0);
@@ -654,26 +730,24 @@ void server_loop(lpdec_server *s)
                     s->results[r.ticket] = std::move(res);
                     s->pending.erase(r.ticket);
                 }
+                s->in_use -= L.footprint;
+                s->slots_in_use -= nf;
                 L.wave.clear();
+                L.busy = false;
                 s->err = "wave launch failed";
                 s->cv_done.notify_all();
-                continue;
             }
-            L.footprint = need;
-            s->in_use += need;
-            s->slots_in_use += nf;
-            L.busy = true;
         }
-        bool any_busy = false;
         for (auto &L : s->lanes) any_busy |= L.busy;
-        if (s->stop && !any_busy && s->queue.empty()) break;
         if (any_busy) {
-            lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(50));
-            lk.lock();
-        } else {
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            continue;
         }
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop && s->queue.empty()) break;
+        if (stop && s->queue.empty()) break;
+        s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        if (s->stop && s->queue.empty()) break;
     }
 }
 
@@ -690,7 +764,7 @@ extern "C" lpdec_status lpdec_server_create(lpdec_ctx *ctx, size_t hbm_budget_by
     s->ctx = ctx;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
-    s->lanes.resize(4);
+    s->lanes.resize(ctx->server_streams);
     for (auto &L : s->lanes) {
         if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
@@ -760,6 +834,7 @@ extern "C" lpdec_status lpdec_server_destroy(lpdec_server *s)
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         ws_free(L.ws);
         ws_free(L.io);
+        if (L.out.h) (void)hipHostFree(L.out.h);
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.stream) (void)hipStreamDestroy(L.stream);
     }

@@ -179,6 +179,8 @@ struct Args {
     uint8_t *xhat;             // [nframes*n]
     int32_t *flag;             // [nframes]
     double *obj;               // [nframes]
+    int32_t *done;             // [nframes], nullable: set to 1 once the frame's outputs are
+                               // visible to the host (outputs in host-mapped memory)
     lpdec_stats *stats;        // [nframes]
     double *u_out;             // [nframes*n]
     uint32_t *trace;           // [nframes*trace_cap*m]

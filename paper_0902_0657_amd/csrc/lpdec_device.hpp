@@ -1745,6 +1745,12 @@ struct Frame {
             st.ticks_pcg = ticks_pcg;
             if (a.stats) a.stats[f] = st;
         }
+        if (a.done) {
+            // every thread's output stores reach the system before the frame is marked done
+            __threadfence_system();
+            __syncthreads();
+            if (tid == 0) __hip_atomic_store(&a.done[f], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 };
 
