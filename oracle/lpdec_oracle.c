@@ -17,6 +17,8 @@
  *     (the standard direct method named in Sec. IV-C), NOT by PCG.
  *   - Algorithm 7 (column-wise greedy search for the maximum-weight triangular set), with
  *     the binary heap of Sec. V-B, and the dependency levels of the two triangular solves.
+ *   - Algorithm 8 (row-wise greedy search) with the diagonal expansion of Sec. V-B, and the
+ *     levels of any triangular set.
  *   - Algorithm 4 (PCG) in FP64 with the preconditioner M = A_M D_M^2 A_M^T of Sec. V,
  *     used only as a reference in tests (the decoder itself uses Cholesky).
  *
@@ -29,7 +31,9 @@
  *   below 1 - tau_viol; a cut is inactive when its slack exceeds max(tau_act, its dual slack);
  *   u_i > 1/2 strict in Algorithm 2 and argmin ties go to the lowest variable index;
  *   Algorithm 7 orders columns by (float(d_i^2) descending, column index ascending), slack
- *   columns numbered after the n standard columns in ascending check order.
+ *   columns numbered after the n standard columns in ascending check order; Algorithm 8
+ *   takes the lowest-indexed degree-1 row and removes the column of smallest
+ *   (float(d_i^2), index).
  */
 #include <math.h>
 #include <stdint.h>
@@ -630,6 +634,115 @@ int orc_mts_levels(int m, int n, const int *rowptr, const int *col, const uint8_
         }
         lev_b[j] = L;
     }
+    free(pairrow);
+    colview_free(&cv);
+    return 0;
+}
+
+/* Algorithm 8: row-wise greedy search for the triangular set, with diagonal expansion.    */
+/* Works on the residual matrix of the LP (rows = checks with a cut, columns = standard    */
+/* columns with at least one such row and the slack of every such row). While a row of     */
+/* residual degree 1 exists, the lowest-indexed one is matched with its only remaining     */
+/* column, which is then removed; otherwise the remaining column of smallest key (w        */
+/* ascending, then column index ascending) is removed unmatched. Rows left unmatched are   */
+/* matched with their own slack column, in ascending order (diagonal expansion).           */
+/* A_M is lower triangular in the returned order: the other matched columns of a row      */
+/* belong to rows matched before it. Same outputs as orc_mts.                              */
+int orc_mts_row(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                const float *w, int *pair, int *order)
+{
+    colview cv;
+    colview_build(&cv, m, n, rowptr, col, hascut);
+    uint8_t *alive = calloc(n + m, 1);     /* column still in the residual matrix */
+    int *rdeg = calloc(m, sizeof(int));    /* remaining columns of each row */
+    int k = 0, live = 0;
+    for (int i = 0; i < n; ++i) alive[i] = cv.cptr[i + 1] > cv.cptr[i];
+    for (int j = 0; j < m; ++j) {
+        pair[j] = -1;
+        if (!hascut[j]) continue;
+        alive[n + j] = 1;
+        rdeg[j] = rowptr[j + 1] - rowptr[j] + 1;
+        ++live;
+    }
+    while (live > 0) {
+        int jr = -1;
+        for (int j = 0; j < m; ++j)
+            if (hascut[j] && pair[j] < 0 && rdeg[j] == 1) { jr = j; break; }
+        int c = -1;
+        if (jr >= 0) {
+            /* the only remaining column of row jr */
+            if (alive[n + jr]) c = n + jr;
+            for (int t = rowptr[jr]; t < rowptr[jr + 1]; ++t) if (alive[col[t]]) c = col[t];
+            pair[jr] = c;
+            order[k++] = jr;
+        } else {
+            for (int i = 0; i < n + m; ++i) {
+                if (!alive[i]) continue;
+                if (c < 0 || w[i] < w[c]) c = i;     /* ascending index breaks ties */
+            }
+            if (c < 0) break;
+        }
+        /* remove column c: each of its rows loses one degree */
+        alive[c] = 0;
+        if (c >= n) {
+            if (--rdeg[c - n] == 0) --live;
+        } else {
+            for (int s2 = cv.cptr[c]; s2 < cv.cptr[c + 1]; ++s2)
+                if (--rdeg[cv.crow[s2]] == 0) --live;
+        }
+    }
+    for (int j = 0; j < m; ++j)
+        if (hascut[j] && pair[j] < 0) { pair[j] = n + j; order[k++] = j; }
+    free(alive); free(rdeg);
+    colview_free(&cv);
+    return k;
+}
+
+/* Dependency levels of the two triangular solves for any triangular set (Sec. V): lev_b[j]
+   = 1 + the largest lev_b over the rows matched with the other preconditioner columns of
+   row j (0 without such rows); lev_f[j] = 1 + the largest lev_f over the other rows of the
+   column matched with row j. Longest chains by memoised depth-first search, without
+   assuming which way the dependencies point. -1 for checks without a cut. */
+static int lvl_b(int j, int n, const int *rowptr, const int *col, const int *pair, const int *pairrow, int *lev)
+{
+    if (lev[j] >= 0) return lev[j];
+    int L = 0;
+    for (int t = rowptr[j]; t < rowptr[j + 1]; ++t) {
+        int i = col[t];
+        if (i == pair[j] || pairrow[i] < 0) continue;
+        int v = lvl_b(pairrow[i], n, rowptr, col, pair, pairrow, lev) + 1;
+        if (v > L) L = v;
+    }
+    return lev[j] = L;
+}
+
+static int lvl_f(int j, int n, const colview *cv, const int *pair, int *lev)
+{
+    if (lev[j] >= 0) return lev[j];
+    int L = 0, c = pair[j];
+    if (c < n)
+        for (int s = cv->cptr[c]; s < cv->cptr[c + 1]; ++s) {
+            int jj = cv->crow[s];
+            if (jj == j) continue;
+            int v = lvl_f(jj, n, cv, pair, lev) + 1;
+            if (v > L) L = v;
+        }
+    return lev[j] = L;
+}
+
+int orc_mts_levels_any(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                       const int *pair, int *lev_b, int *lev_f)
+{
+    colview cv;
+    colview_build(&cv, m, n, rowptr, col, hascut);
+    int *pairrow = malloc(sizeof(int) * (n + 1));
+    for (int i = 0; i < n; ++i) pairrow[i] = -1;
+    for (int j = 0; j < m; ++j) {
+        lev_b[j] = -1; lev_f[j] = -1;
+        if (hascut[j] && pair[j] >= 0 && pair[j] < n) pairrow[pair[j]] = j;
+    }
+    for (int j = 0; j < m; ++j)
+        if (hascut[j]) { lvl_b(j, n, rowptr, col, pair, pairrow, lev_b); lvl_f(j, n, &cv, pair, lev_f); }
     free(pairrow);
     colview_free(&cv);
     return 0;

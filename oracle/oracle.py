@@ -185,6 +185,28 @@ def mts(code, hascut, w):
     return pair, order[:p]
 
 
+def mts_row(code, hascut, w):
+    """Algorithm 8 (row-wise greedy search) with diagonal expansion. w: float32 weights, n+m
+    entries. Returns (pair[m], order[p]); A_M is lower triangular in that order."""
+    hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    pair = np.full(code.m, -1, dtype=np.int32)
+    order = np.zeros(code.m + 1, dtype=np.int32)
+    p = _L().orc_mts_row(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
+                         _p(hascut), _p(w), _p(pair), _p(order))
+    return pair, order[:p]
+
+
+def mts_levels_any(code, hascut, pair):
+    """Levels of the two triangular solves for any triangular set (longest dependency chains)."""
+    hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
+    lb = np.zeros(code.m, dtype=np.int32)
+    lf = np.zeros(code.m, dtype=np.int32)
+    _L().orc_mts_levels_any(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
+                            _p(hascut), _p(_i32(pair)), _p(lb), _p(lf))
+    return lb, lf
+
+
 def mts_levels(code, hascut, pair, order):
     hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
     lb = np.zeros(code.m, dtype=np.int32)

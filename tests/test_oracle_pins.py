@@ -443,3 +443,104 @@ def test_stalled_ipm_floor_rule(orc):
         fun, _ = refs.feldman_lp(code, gamma)
         scale = 1.0 + abs(fun - gamma[gamma < 0].sum())
         assert abs(res.objective - fun) <= 1e-7 * scale
+
+
+# ---------------------------------------------------------------- Algorithm 8 + levels
+def mts_row_dense(code, hascut, w):
+    """Algorithm 8 on an explicit 0/1 residual matrix (rows = checks with a cut, columns = the
+    n standard columns and the m slacks), zeroing columns as the algorithm states: the
+    lowest-indexed row of degree 1 is matched with its column; with no such row the nonzero
+    column of smallest (float32 weight, index) is zeroed; unmatched rows get their slack."""
+    n, m = code.n, code.m
+    H = code.dense()
+    A = np.zeros((m, n + m), dtype=np.int8)
+    for j in range(m):
+        if hascut[j]:
+            A[j, :n] = H[j]
+            A[j, n + j] = 1
+    pair = np.full(m, -1, dtype=np.int32)
+    order = []
+    while A.any():
+        rows1 = np.nonzero(A.sum(axis=1) == 1)[0]
+        if len(rows1):
+            j = int(rows1[0])
+            i = int(np.nonzero(A[j])[0][0])
+            pair[j] = i
+            order.append(j)
+        else:
+            i = min((np.float32(w[c]), int(c)) for c in np.nonzero(A.any(axis=0))[0])[1]
+        A[:, i] = 0
+    for j in range(m):
+        if hascut[j] and pair[j] < 0:
+            pair[j] = n + j
+            order.append(j)
+    return pair, np.array(order, dtype=np.int32)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "ties", "spread"])
+def test_mts_row_equals_dense_and_is_lower_triangular(orc, kind):
+    rng = np.random.Generator(np.random.PCG64(29))
+    for n in (48, 96, 150):
+        code = regular_code(n) if n >= 60 else regular_code(n, no4=False)
+        H = code.dense()
+        for _ in range(5):
+            hascut = (rng.random(code.m) < 0.8).astype(np.uint8)
+            w = _weights(rng, code.n + code.m, kind)
+            pair, order = orc.mts_row(code, hascut, w)
+            p2, o2 = mts_row_dense(code, hascut, w)
+            assert np.array_equal(pair, p2) and np.array_equal(order, o2)
+            p = int(hascut.sum())
+            assert len(order) == p and len(set(order.tolist())) == p
+            cols = [int(pair[j]) for j in order]
+            assert len(set(cols)) == p
+            # rows and columns in matching order: lower triangular with a nonzero diagonal
+            for k, j in enumerate(order):
+                for l, c in enumerate(cols):
+                    nz = (c >= code.n and c - code.n == j) or (c < code.n and H[j, c])
+                    if l == k:
+                        assert nz
+                    elif l > k:
+                        assert not nz
+
+
+def test_mts_row_single_check_keeps_heaviest_column(orc):
+    """One check with a cut: no row has degree 1 until every column but one is gone, and the
+    lightest go first, so the row is matched with its heaviest column (slack included)."""
+    code = from_dense(np.array([[1, 1, 1, 1, 1, 0], [0, 1, 1, 1, 0, 1]], dtype=np.int8))
+    rng = np.random.Generator(np.random.PCG64(31))
+    for _ in range(20):
+        w = rng.random(code.n + code.m).astype(np.float32)
+        pair, order = orc.mts_row(code, np.array([1, 0], dtype=np.uint8), w)
+        cand = list(code.row(0)) + [code.n + 0]
+        assert pair[0] == max(cand, key=lambda c: (w[c], -c)) and pair[1] == -1
+        assert order.tolist() == [0]
+
+
+def test_levels_any_equals_ordered_levels_and_longest_chains(orc):
+    """The order-free level computation agrees with the elimination-order one on Algorithm 7
+    sets, and equals the longest dependency chains on Algorithm 8 sets."""
+    rng = np.random.Generator(np.random.PCG64(37))
+    code = regular_code(120)
+    n = code.n
+    for _ in range(6):
+        hascut = (rng.random(code.m) < 0.75).astype(np.uint8)
+        w = _weights(rng, code.n + code.m, "spread")
+        pair, order = orc.mts(code, hascut, w)
+        lb, lf = orc.mts_levels(code, hascut, pair, order)
+        lb2, lf2 = orc.mts_levels_any(code, hascut, pair)
+        assert np.array_equal(lb, lb2) and np.array_equal(lf, lf2)
+        pair, order = orc.mts_row(code, hascut, w)
+        lb, lf = orc.mts_levels_any(code, hascut, pair)
+        pairrow = {int(pair[j]): j for j in range(code.m) if pair[j] >= 0}
+        rows_of = {i: [j for j in range(code.m) if hascut[j] and i in code.row(j)] for i in range(n)}
+        # longest chains by repeated relaxation (Bellman-Ford on the dependency graph)
+        db = {j: [pairrow[int(i)] for i in code.row(j) if int(i) != pair[j] and int(i) in pairrow]
+              for j in range(code.m) if hascut[j]}
+        df = {j: ([] if pair[j] >= n else [r for r in rows_of[int(pair[j])] if r != j])
+              for j in range(code.m) if hascut[j]}
+        for deps, lev in ((db, lb), (df, lf)):
+            L = {j: 0 for j in deps}
+            for _ in range(len(deps) + 1):
+                L = {j: (1 + max(L[k] for k in d)) if d else 0 for j, d in deps.items()}
+            for j in deps:
+                assert lev[j] == L[j]
