@@ -50,6 +50,7 @@ struct Plan {
     size_t pair, pairrow, lbv, lfv, order;     // i16 [m], [n], [m], [m], [m]
     size_t boff, foff;                         // i32 [m+1]
     size_t deg, sg;                            // u8 / i8 [n]
+    size_t rdeg, r1;                           // Algorithm 8: u8 [m] row degrees, u32 [(m+31)/32] degree-1 rows
     size_t vmask;                              // u32 [m]
     size_t rank, lcol, lmask;                  // u8 [n+m], u16 [64*lanecols], u32 [64*maskwords]
     size_t hot_bytes;
@@ -115,6 +116,8 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.order = o; o = lp_align(o + 2 * M);
     p.deg = o; o = lp_align(o + N);
     p.sg = o; o = lp_align(o + N);
+    p.rdeg = o; o = lp_align(o + M);
+    p.r1 = o; o = lp_align(o + 4 * ((M + 31) / 32));
     p.hot_bytes = o;
     o = 0;
     p.x = o; o = lp_align(o + 8 * Q);

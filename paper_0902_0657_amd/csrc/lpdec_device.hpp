@@ -432,6 +432,8 @@ struct Frame {
     uint8_t *rank;       // rank of a column among the columns of its lane (Algorithm 7)
     uint16_t *lcol;      // the columns of each lane by rank: lcol[r * 64 + lane]
     uint32_t *lmask;     // available columns of each lane by rank: word w at lmask[w * 64 + lane]
+    uint8_t *rdeg;       // Algorithm 8: remaining columns of each row
+    uint32_t *r1m;       // Algorithm 8: rows with one remaining column, one bit per check
     int RWC, CWC, MW;    // chunks per row slot, per column slot; mask words per lane
     // cold
     double *x, *z, *dx, *dz, *rc, *tq, *d2, *y, *dy, *rb, *w, *b, *rho, *f64, *u, *g;
@@ -468,6 +470,7 @@ struct Frame {
         boff = (int *)(hot + P.boff); foff = (int *)(hot + P.foff);
         deg = (uint8_t *)(hot + P.deg); sg = (int8_t *)(hot + P.sg); vmask = (uint32_t *)(hot + P.vmask);
         rank = (uint8_t *)(hot + P.rank); lcol = (uint16_t *)(hot + P.lcol); lmask = (uint32_t *)(hot + P.lmask);
+        rdeg = (uint8_t *)(hot + P.rdeg); r1m = (uint32_t *)(hot + P.r1);
         x = (double *)(cold + P.x); z = (double *)(cold + P.z); dx = (double *)(cold + P.dx);
         dz = (double *)(cold + P.dz); rc = (double *)(cold + P.rc); tq = (double *)(cold + P.tq);
         d2 = (double *)(cold + P.d2); y = (double *)(cold + P.y); dy = (double *)(cold + P.dy);
@@ -729,6 +732,178 @@ struct Frame {
                 const int lv = lbv[dd != kEnd ? dd : 0];
                 const int L = (int)wave_max_u32(dd != kEnd ? (uint32_t)(lv + 1) : 0u);
                 if (lane == 0) lbv[row] = (int16_t)L;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        return pl;
+    }
+
+    // Row-wise greedy search for the triangular set (Algorithm 8) with diagonal expansion.
+    //   The residual matrix holds the LP rows and the columns that still have entries there.
+    //   rdeg counts each row's remaining columns, r1m marks the rows with exactly one, and the
+    //   per-lane masks of Algorithm 7 mark the remaining columns, ranked per lane by
+    //   (weight, index) ascending so that a lane's lowest set bit is its lightest column.
+    //   Wave 0 runs the steps: the lowest-indexed row of degree 1 is matched with its only
+    //   remaining column (the row's lanes find it); without such a row the lightest remaining
+    //   column (wave minimum) is removed unmatched. Removing a column lowers the degree of
+    //   each of its rows. Rows left unmatched then take their slack, in ascending order.
+    //   A_M is lower triangular in matching order, so back-substitution dependencies point to
+    //   rows matched earlier and forward ones to rows matched later: the levels are computed
+    //   walking the order forward and backward respectively. Fills pair, pairrow, order, lbv,
+    //   lfv as mts() does. Returns p.
+    LPD_INLINE unsigned long long rowkey(const float *wk, int c) const
+    {
+        return ((unsigned long long)__float_as_uint(wt(wk, c)) << 32) | (unsigned long long)(unsigned)c;
+    }
+    LPD_INLINE bool col_left(int c) const
+    {
+        const int r = rank[c];
+        return (lmask[(r >> 5) * 64 + (c & 63)] >> (r & 31)) & 1u;
+    }
+    LPD_INLINE int mts_row(const float *wk)
+    {
+        const int r1w = (m + 31) >> 5;
+        for (int i = tid; i < n; i += nt) {
+            int dg = 0;
+            for (int ch = 0; ch < CWC; ++ch) {
+                Ch4 E;
+                ldch(E, clist + (size_t)i * CW + 4 * ch);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dg += at(E, k) != kEnd;
+            }
+            deg[i] = (uint8_t)dg;
+            pairrow[i] = -1;
+        }
+        int pl = 0;
+        for (int j = tid; j < m; j += nt) {
+            pair[j] = -1; lfv[j] = -1; lbv[j] = -1;
+            int d = 0;
+            if (cut(j)) {
+                ++pl;
+                d = 1;   // the slack
+                for (int k = 0; k < RW; ++k) d += rlist[(size_t)j * RW + k] != kEnd;
+            }
+            rdeg[j] = (uint8_t)d;
+        }
+        for (int k = tid; k < 64 * MW; k += nt) lmask[k] = 0u;
+        for (int k = tid; k < r1w; k += nt) r1m[k] = 0u;
+        pl = block_sum1(pl, sc);
+        p = pl;
+        // rank of each remaining column among the remaining columns of its lane, ascending key
+        for (int c = tid; c < n + m; c += nt) {
+            if (!present(c) || (c < n && deg[c] == 0)) continue;
+            const unsigned long long kc = rowkey(wk, c);
+            int r = 0;
+            for (int c2 = c & 63; c2 < n + m; c2 += 64)
+                r += present(c2) && (c2 >= n || deg[c2] > 0) && rowkey(wk, c2) < kc;
+            rank[c] = (uint8_t)r;
+            lcol[r * 64 + (c & 63)] = (uint16_t)c;
+        }
+        __syncthreads();
+        for (int c = tid; c < n + m; c += nt)
+            if (present(c) && (c >= n || deg[c] > 0)) mask_set(c, true);
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            int k = 0, live = pl;   // rows with remaining columns
+            while (live > 0) {
+                __builtin_amdgcn_wave_barrier();
+                int cand = 0x7FFFFFFF;
+                for (int wd = lane; wd < r1w; wd += 64) {
+                    const uint32_t b = r1m[wd];
+                    if (b) { cand = wd * 32 + __builtin_ctz(b); break; }
+                }
+                const int jr = wave_min_t(cand);
+                int c;
+                if (jr != 0x7FFFFFFF) {
+                    // the only remaining column of row jr: lane q < RW looks at entry q, lane
+                    // RW at the slack
+                    int cl = -1;
+                    if (lane < RW) {
+                        const uint16_t e = rlist[(size_t)jr * RW + lane];
+                        cl = e != kEnd ? e_idx(e) : -1;
+                    } else if (lane == RW) {
+                        cl = n + jr;
+                    }
+                    c = wave_max_t(cl >= 0 && col_left(cl) ? cl : -1);
+                    if (c < 0) break;   // cannot happen: a degree-1 row has its column
+                    if (lane == 0) {
+                        pair[jr] = (int16_t)c;
+                        order[k] = (int16_t)jr;
+                        if (c < n) pairrow[c] = (int16_t)jr;
+                    }
+                    ++k;
+                } else {
+                    int r = -1;
+                    for (int wd = 0; wd < MW && r < 0; ++wd) {
+                        const uint32_t bits = lmask[wd * 64 + lane];
+                        if (bits) r = wd * 32 + __builtin_ctz(bits);
+                    }
+                    const unsigned long long key = r >= 0 ? rowkey(wk, (int)lcol[r * 64 + lane]) : ~0ull;
+                    const unsigned long long K = ~wave_max_u64(~key);
+                    if (K == ~0ull) break;   // no column left: cannot happen while rows have some
+                    c = (int)(unsigned)(K & 0xFFFFFFFFull);
+                }
+                // remove column c: its rows lose one degree
+                const int rk = rank[c];
+                int jj = -1;
+                if (c >= n) {
+                    jj = lane == 0 ? c - n : -1;
+                } else if (lane < CW) {
+                    const uint16_t e = clist[(size_t)c * CW + lane];
+                    jj = e != kEnd ? e_idx(e) : -1;
+                }
+                const int nd = jj >= 0 ? (int)rdeg[jj] - 1 : -1;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) atomicAnd(&lmask[(rk >> 5) * 64 + (c & 63)], ~(1u << (rk & 31)));
+                if (jj >= 0) {
+                    rdeg[jj] = (uint8_t)nd;
+                    uint32_t *wp = &r1m[jj >> 5];
+                    if (nd == 1) atomicOr(wp, 1u << (jj & 31));
+                    else if (nd == 0) atomicAnd(wp, ~(1u << (jj & 31)));
+                }
+                live -= __popcll(__ballot(nd == 0));
+            }
+            // diagonal expansion: the unmatched rows with a cut take their slack, ascending
+            __builtin_amdgcn_wave_barrier();
+            for (int base = 0; base < m; base += 64) {
+                const int j = base + lane;
+                const bool un = j < m && cut(j) && pair[j] < 0;
+                const unsigned long long bal = __ballot(un);
+                if (un) {
+                    pair[j] = (int16_t)(n + j);
+                    order[k + __popcll(bal & ((1ull << lane) - 1ull))] = (int16_t)j;
+                }
+                k += __popcll(bal);
+            }
+            // levels: back-substitution dependencies (the rows of the row's other matched
+            // columns) were matched earlier, forward ones (the other rows of the row's column)
+            // later
+            __builtin_amdgcn_wave_barrier();
+            for (int step = 0; step < k; ++step) {
+                const int row = order[step];
+                int L = 0;
+                if (lane < RW) {
+                    const uint16_t e = rlist[(size_t)row * RW + lane];
+                    const int i = e != kEnd ? e_idx(e) : -1;
+                    const int pr = i >= 0 && i != pair[row] ? (int)pairrow[i] : -1;
+                    L = pr >= 0 ? lbv[pr] + 1 : 0;
+                }
+                L = wave_max_t(L);
+                if (lane == 0) lbv[row] = (int16_t)L;
+                __builtin_amdgcn_wave_barrier();
+            }
+            for (int step = k - 1; step >= 0; --step) {
+                const int row = order[step], c = pair[row];
+                int L = 0;
+                if (c < n && lane < CW) {
+                    const uint16_t e = clist[(size_t)c * CW + lane];
+                    const int jj = e != kEnd ? e_idx(e) : -1;
+                    L = jj >= 0 && jj != row ? lfv[jj] + 1 : 0;
+                }
+                L = wave_max_t(L);
+                if (lane == 0) lfv[row] = (int16_t)L;
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -1595,7 +1770,8 @@ struct Frame {
             const long long t0 = wall_clock64();
             const bool search = it % o.mts_reuse == 0;
             if (!direct_mode && search) {
-                if (o.precond) mts(nullptr);
+                if (o.precond == 1) mts(nullptr);
+                else if (o.precond == 2) mts_row(nullptr);
                 else slack_basis();
                 build_levels();
                 st.max_levels = max(st.max_levels, max(nlb, nlf));

@@ -169,11 +169,12 @@ def test_edge_cases(ctx, orc):
     assert empty["flag"].numel() == 0
 
 
-@pytest.mark.parametrize("opt,val", [("MTS_REUSE", 2), ("MTS_REUSE", 4), ("WARM_START", 1)])
+@pytest.mark.parametrize("opt,val", [("MTS_REUSE", 2), ("MTS_REUSE", 4), ("WARM_START", 1), ("PRECOND", 2)])
 def test_preconditioner_reuse_and_warm_start(ctx, orc, opt, val):
-    """The preconditioning set kept over several IPM iterations of an LP (MTS_REUSE), or each
-    Newton solve started from the previous direction (WARM_START): the decode still equals the
-    oracle's; reuse runs fewer triangular-set searches."""
+    """The preconditioning set kept over several IPM iterations of an LP (MTS_REUSE), each
+    Newton solve started from the previous direction (WARM_START), or the preconditioner
+    from Algorithm 8 (PRECOND 2): the decode still equals the oracle's; reuse runs fewer
+    triangular-set searches."""
     import torch
     from paper_0902_0657_amd import stats_table
     code = regular_code(256)
