@@ -128,6 +128,10 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   WARM_START     1 = from the second IPM iteration of an LP on, a Newton solve starts from
  *                  the previous direction dy when that leaves a smaller residual than 0
  *                  (Algorithm 4's initial guess); 0 (default) = starts from 0
+ *   IPM_WARM       theta >= 0: with theta > 0, every LP after a decode's first starts the
+ *                  IPM from the previous LP's x + theta, z + theta (and its y) on the columns
+ *                  and cuts the two LPs share, new cuts from x = z = 1, y = 0; 0 (default) =
+ *                  every LP starts from x = e, y = 0, z = e
  *   SERVER_STREAMS HIP streams (waves in flight) of a server created afterwards (1..32, 8).
  *                  Streams beyond the process's hardware queues (HIP's GPU_MAX_HW_QUEUES,
  *                  4 unless set before HIP starts) share queues and their waves serialize
@@ -138,7 +142,7 @@ enum {
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
     LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT_MTS_REUSE, LPDEC_OPT_WARM_START,
-    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT__COUNT
+    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);

@@ -105,6 +105,7 @@ void default_opts(lpdec::Opts &o)
     o.direct = 1;
     o.mts_reuse = 1;
     o.warm = 0;
+    o.ipm_warm = 0.0;
     o.tau_viol = 1e-4;
     o.tau_act = 1e-4;
     o.tau_int = 1e-4;
@@ -238,6 +239,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_DIRECT_FALLBACK: if (v != 0 && v != 1) break; o.direct = (int)v; return LPDEC_OK;
     case LPDEC_OPT_MTS_REUSE: if (!ipos(1) || v > 1000) break; o.mts_reuse = (int)v; return LPDEC_OK;
     case LPDEC_OPT_WARM_START: if (v != 0 && v != 1) break; o.warm = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_IPM_WARM: if (!(v >= 0 && v <= 10)) break; o.ipm_warm = v; return LPDEC_OK;
     default: return fail(ctx, LPDEC_EINVAL, "unknown option key %d", key);
     }
     return fail(ctx, LPDEC_EINVAL, "bad value %g for option %d", v, key);
@@ -270,6 +272,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_DIRECT_FALLBACK: *v = o.direct; break;
     case LPDEC_OPT_MTS_REUSE: *v = o.mts_reuse; break;
     case LPDEC_OPT_WARM_START: *v = o.warm; break;
+    case LPDEC_OPT_IPM_WARM: *v = o.ipm_warm; break;
     default: return LPDEC_EINVAL;
     }
     return LPDEC_OK;

@@ -18,6 +18,7 @@ struct Opts {
     int direct;      // 1: dense Cholesky fallback for Newton solves PCG does not finish
     int mts_reuse;   // the triangular set is searched on every mts_reuse-th IPM iteration of an LP
     int warm;        // 1: a Newton solve starts from the previous direction of the same LP
+    double ipm_warm; // > 0: an LP after the first starts from the previous LP's point, shifted by this
     double tau_viol, tau_act, tau_int;
     double eps, eps_stall, sigma, eta;
     double pcg_tol, ref_tol, xi_tol;
@@ -62,6 +63,7 @@ struct Plan {
     size_t ridx, colk, dense;                  // dense fallback: i32 [m+1], FP64 [mp], FP64 [mp*mp], mp = m rounded up to kDenseTile
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
+    size_t vprev;                              // u32 [m]: cut of each check in the previous LP
     size_t cold_bytes;
 };
 
@@ -145,6 +147,7 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.u = o; o = lp_align(o + 8 * N);
     p.g = o; o = lp_align(o + 8 * N);
     p.active = o; o = lp_align(o + M);
+    p.vprev = o; o = lp_align(o + 4 * M);
     p.cold_bytes = o;
     return p;
 }

@@ -443,6 +443,8 @@ struct Frame {
     double *colk, *qd;   // dense fallback: work vector, the p x p matrix (null when absent)
     double *ldsd;        // dense fallback: factor of the diagonal tile, reciprocals, vector block (LDS)
     uint8_t *active;
+    uint32_t *vprev;     // cut of each check in the previous LP of this decode
+    bool have_prev;      // an LP of this decode has been solved
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
     int Z;                 // index of the zero slot of the PCG vector space (n + 2m)
@@ -479,6 +481,8 @@ struct Frame {
         u = (double *)(cold + P.u); g = (double *)(cold + P.g);
         for (int k = 0; k < 8; ++k) c64[k] = (double *)(cold + P.c64 + (size_t)k * lp_align(8 * (size_t)m));
         active = (uint8_t *)(cold + P.active);
+        vprev = (uint32_t *)(cold + P.vprev);
+        have_prev = false;
     }
 
     LPD_INLINE bool cut(int j) const { return vmask[j] != 0u; }
@@ -1685,6 +1689,12 @@ struct Frame {
     {
         double a0[2] = {0.0, 0.0};
         int pl = 0;
+        // start point: x = e, y = 0, z = e; with IPM_WARM = theta > 0 an LP after the first
+        // starts from the previous LP's point shifted into the interior (x + theta, z +
+        // theta; y kept) on the columns and rows it shares with that LP (the method accepts
+        // any x > 0, z > 0, Sec. IV-B)
+        const double th = o.ipm_warm;
+        const bool warm = th > 0.0 && have_prev;
         for (int j = tid; j < m; j += nt) {
             if (cut(j)) {
                 // b of the flipped parity inequality: |V| - 1 - sum of its u-coefficients
@@ -1700,15 +1710,20 @@ struct Frame {
                 const double bj = (double)(vsz - 1 - sneg);
                 b[j] = bj;
                 a0[0] += bj * bj;
-                x[n + j] = 1.0; z[n + j] = 1.0;
+                if (warm && vprev[j] == V) {
+                    x[n + j] += th; z[n + j] += th;
+                } else {
+                    x[n + j] = 1.0; z[n + j] = 1.0; y[j] = 0.0;
+                }
                 ++pl;
             } else {
-                b[j] = 0.0; x[n + j] = 0.0; z[n + j] = 0.0;
+                b[j] = 0.0; x[n + j] = 0.0; z[n + j] = 0.0; y[j] = 0.0;
             }
-            y[j] = 0.0;
+            vprev[j] = cut(j) ? vmask[j] : 0u;
         }
         for (int i = tid; i < n; i += nt) {
-            x[i] = 1.0; z[i] = 1.0;
+            if (warm) { x[i] += th; z[i] += th; }
+            else { x[i] = 1.0; z[i] = 1.0; }
             a0[1] += g[i] * g[i];
         }
         block_sum<2>(a0, sc);
@@ -1855,7 +1870,8 @@ struct Frame {
         const long long t_start = wall_clock64();
         load_gamma(a, f);
         for (int i = tid; i < n; i += nt) u[i] = g[i] >= 0.0 ? 0.0 : 1.0;   // hard decision
-        for (int j = tid; j < m; j += nt) { vmask[j] = 0u; active[j] = 0; }
+        for (int j = tid; j < m; j += nt) { vmask[j] = 0u; active[j] = 0; vprev[j] = 0u; }
+        have_prev = false;
         __syncthreads();
         int status = 0, k;
         for (k = 0; k < o.malp_max; ++k) {
@@ -1874,6 +1890,7 @@ struct Frame {
             build_lists();
             int its = 0;
             status = ipm(st, its);
+            have_prev = status >= 0;
             st.malp_iters++;
             st.ipm_iters += its;
             st.p_max = max(st.p_max, p);
