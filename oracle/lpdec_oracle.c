@@ -17,8 +17,8 @@
  *     (the standard direct method named in Sec. IV-C), NOT by PCG.
  *   - Algorithm 7 (column-wise greedy search for the maximum-weight triangular set), with
  *     the binary heap of Sec. V-B, and the dependency levels of the two triangular solves.
- *   - Algorithm 8 (row-wise greedy search) with the diagonal expansion of Sec. V-B, and the
- *     levels of any triangular set.
+ *   - Algorithm 8 (row-wise greedy search) with the diagonal or the triangular expansion of
+ *     Sec. V-B, and the levels of any triangular set.
  *   - Algorithm 4 (PCG) in FP64 with the preconditioner M = A_M D_M^2 A_M^T of Sec. V,
  *     used only as a reference in tests (the decoder itself uses Cholesky).
  *
@@ -648,8 +648,21 @@ int orc_mts_levels(int m, int n, const int *rowptr, const int *col, const uint8_
 /* matched with their own slack column, in ascending order (diagonal expansion).           */
 /* A_M is lower triangular in the returned order: the other matched columns of a row      */
 /* belong to rows matched before it. Same outputs as orc_mts.                              */
+int orc_mts_row2(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                 const float *w, int expand, int *pair, int *order);
+
 int orc_mts_row(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
                 const float *w, int *pair, int *order)
+{
+    return orc_mts_row2(m, n, rowptr, col, hascut, w, 0, pair, order);
+}
+
+/* expand = 0: diagonal expansion; 1: triangular expansion -- the rows left unmatched are
+   matched by the column-wise greedy search (Algorithm 7's rule: the degree-1 column of
+   largest key, w descending then index ascending) on the columns whose rows are all
+   unmatched (the matrix A-bar of Sec. V-B), after the rows of the row-wise phase. */
+int orc_mts_row2(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                 const float *w, int expand, int *pair, int *order)
 {
     colview cv;
     colview_build(&cv, m, n, rowptr, col, hascut);
@@ -690,6 +703,38 @@ int orc_mts_row(int m, int n, const int *rowptr, const int *col, const uint8_t *
             for (int s2 = cv.cptr[c]; s2 < cv.cptr[c + 1]; ++s2)
                 if (--rdeg[cv.crow[s2]] == 0) --live;
         }
+    }
+    if (expand == 1) {
+        /* A-bar: columns all of whose LP rows are unmatched; greedy by columns over it */
+        int *deg = calloc(n + m, sizeof(int));      /* live rows of each A-bar column, -1 outside */
+        uint8_t *live = calloc(m, 1);
+        int left = 0;
+        for (int j = 0; j < m; ++j) if (hascut[j] && pair[j] < 0) { live[j] = 1; ++left; }
+        for (int i = 0; i < n; ++i) {
+            int d = cv.cptr[i + 1] - cv.cptr[i];
+            for (int s2 = cv.cptr[i]; s2 < cv.cptr[i + 1]; ++s2) if (!live[cv.crow[s2]]) d = -1;
+            deg[i] = d > 0 ? d : -1;
+        }
+        for (int j = 0; j < m; ++j) deg[n + j] = live[j] ? 1 : -1;
+        while (left > 0) {
+            int c = -1;
+            for (int i = 0; i < n + m; ++i)
+                if (deg[i] == 1 && (c < 0 || w[i] > w[c])) c = i;   /* ascending index breaks ties */
+            if (c < 0) break;
+            int row = -1;
+            if (c >= n) row = c - n;
+            else
+                for (int s2 = cv.cptr[c]; s2 < cv.cptr[c + 1]; ++s2) if (live[cv.crow[s2]]) row = cv.crow[s2];
+            pair[row] = c;
+            order[k++] = row;
+            live[row] = 0;
+            --left;
+            deg[c] = -1;
+            if (c != n + row) deg[n + row] = -1;
+            for (int t = rowptr[row]; t < rowptr[row + 1]; ++t)
+                if (col[t] != c && deg[col[t]] > 0) deg[col[t]]--;
+        }
+        free(deg); free(live);
     }
     for (int j = 0; j < m; ++j)
         if (hascut[j] && pair[j] < 0) { pair[j] = n + j; order[k++] = j; }

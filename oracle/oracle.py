@@ -185,15 +185,16 @@ def mts(code, hascut, w):
     return pair, order[:p]
 
 
-def mts_row(code, hascut, w):
-    """Algorithm 8 (row-wise greedy search) with diagonal expansion. w: float32 weights, n+m
-    entries. Returns (pair[m], order[p]); A_M is lower triangular in that order."""
+def mts_row(code, hascut, w, expand=0):
+    """Algorithm 8 (row-wise greedy search) with the diagonal (expand=0) or the triangular
+    (expand=1) expansion. w: float32 weights, n+m entries. Returns (pair[m], order[p]); with
+    the diagonal expansion A_M is lower triangular in that order."""
     hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
     w = np.ascontiguousarray(w, dtype=np.float32)
     pair = np.full(code.m, -1, dtype=np.int32)
     order = np.zeros(code.m + 1, dtype=np.int32)
-    p = _L().orc_mts_row(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
-                         _p(hascut), _p(w), _p(pair), _p(order))
+    p = _L().orc_mts_row2(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
+                          _p(hascut), _p(w), C.c_int(expand), _p(pair), _p(order))
     return pair, order[:p]
 
 

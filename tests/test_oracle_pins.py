@@ -544,3 +544,103 @@ def test_levels_any_equals_ordered_levels_and_longest_chains(orc):
                 L = {j: (1 + max(L[k] for k in d)) if d else 0 for j, d in deps.items()}
             for j in deps:
                 assert lev[j] == L[j]
+
+
+def triangulation_step(code, hascut, pair):
+    """Algorithm 5 on the preconditioning columns: repeatedly take a row with exactly one
+    remaining column of the set and remove that column. Succeeds (returns True) iff A_M can
+    be brought into triangular form by row and column permutations."""
+    n = code.n
+    H = code.dense()
+    rows = [j for j in range(code.m) if hascut[j]]
+    cols = {int(pair[j]) for j in rows}
+
+    def nz(j, c):
+        return (c >= n and c - n == j) or (c < n and H[j, c] != 0)
+    left_rows, left_cols = set(rows), set(cols)
+    while left_rows:
+        pick = None
+        for j in sorted(left_rows):
+            cs = [c for c in left_cols if nz(j, c)]
+            if len(cs) == 1:
+                pick = (j, cs[0])
+                break
+        if pick is None:
+            return False
+        left_rows.discard(pick[0])
+        left_cols.discard(pick[1])
+    return True
+
+
+def mts_row_tri_dense(code, hascut, w):
+    """Algorithm 8 with triangular expansion on explicit matrices: the row-wise phase of
+    mts_row_dense without its diagonal expansion, then the column-wise greedy search (largest
+    (weight, -index) degree-1 column) on A-bar, the columns with no entry in a matched row."""
+    n, m = code.n, code.m
+    H = code.dense()
+    A = np.zeros((m, n + m), dtype=np.int8)
+    for j in range(m):
+        if hascut[j]:
+            A[j, :n] = H[j]
+            A[j, n + j] = 1
+    full = A.copy()
+    pair = np.full(m, -1, dtype=np.int32)
+    order = []
+    while A.any():
+        rows1 = np.nonzero(A.sum(axis=1) == 1)[0]
+        if len(rows1):
+            j = int(rows1[0])
+            i = int(np.nonzero(A[j])[0][0])
+            pair[j] = i
+            order.append(j)
+        else:
+            i = min((np.float32(w[c]), int(c)) for c in np.nonzero(A.any(axis=0))[0])[1]
+        A[:, i] = 0
+    unmatched = [j for j in range(m) if hascut[j] and pair[j] < 0]
+    matched = [j for j in range(m) if pair[j] >= 0]
+    B = full.copy()
+    B[matched, :] = 0
+    bar = [c for c in range(n + m) if full[:, c].any() and not full[matched, c].any()]
+    B = B[:, bar]
+    live = set(unmatched)
+    while live:
+        best = None
+        for k, c in enumerate(bar):
+            rs = [j for j in live if B[j, k]]
+            if len(rs) == 1 and (best is None or (np.float32(w[c]), -c) > best[0]):
+                best = ((np.float32(w[c]), -c), c, rs[0])
+        _, c, j = best
+        pair[j] = c
+        order.append(j)
+        live.discard(j)
+        B[j, :] = 0
+    return pair, np.array(order, dtype=np.int32)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "ties", "spread"])
+def test_mts_row_triangular_expansion_equals_dense_and_triangulates(orc, kind):
+    rng = np.random.Generator(np.random.PCG64(41))
+    for n in (48, 96):
+        code = regular_code(n) if n >= 60 else regular_code(n, no4=False)
+        for _ in range(5):
+            hascut = (rng.random(code.m) < 0.8).astype(np.uint8)
+            w = _weights(rng, code.n + code.m, kind)
+            pair, order = orc.mts_row(code, hascut, w, expand=1)
+            p2, o2 = mts_row_tri_dense(code, hascut, w)
+            assert np.array_equal(pair, p2) and np.array_equal(order, o2)
+            p = int(hascut.sum())
+            assert len(order) == p and len({int(pair[j]) for j in order}) == p
+            assert triangulation_step(code, hascut, pair)
+            # the row-wise phase is the same for both expansions: rows that the diagonal
+            # expansion did not give their slack keep their column
+            pd, od = orc.mts_row(code, hascut, w, expand=0)
+            for j in od:
+                if pd[j] != code.n + j:
+                    assert pair[j] == pd[j]
+
+
+def test_triangulation_step_rejects_a_cycle(orc):
+    """Algorithm 5 itself: the 2 x 2 all-ones block (a 4-cycle) cannot be triangularised."""
+    code = from_dense(np.array([[1, 1, 0], [1, 1, 1]], dtype=np.int8))
+    assert not triangulation_step(code, np.array([1, 1], np.uint8), np.array([0, 1], np.int32))
+    assert triangulation_step(code, np.array([1, 1], np.uint8), np.array([0, 2], np.int32))
