@@ -112,7 +112,9 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   BLOCK          threads per frame (64..256, multiple of 64; 0 = automatic)
  *   PRECOND        1 = triangular preconditioner from Algorithm 7 (column-wise greedy,
  *                  default), 2 = from Algorithm 8 (row-wise greedy, diagonal expansion),
- *                  0 = the slack columns as preconditioning set (a diagonal preconditioner)
+ *                  3 = Algorithm 8 with triangular expansion (the unmatched rows by the
+ *                  column-wise greedy over the columns of unmatched rows only), 0 = the slack
+ *                  columns as preconditioning set (a diagonal preconditioner)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
  *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
@@ -194,9 +196,9 @@ lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int3
 
 /* The triangular-set search of the context's PRECOND on the LP whose rows are the checks
  * with hascut_dev[f*m+j] != 0: Algorithm 7 (PRECOND 1 or 0; columns ordered by weight
- * descending, then index ascending) or Algorithm 8 with diagonal expansion (PRECOND 2; the
- * lowest-indexed row of degree 1 first, columns removed by weight ascending, then index
- * ascending). Column weights w_dev float[nframes*(n+m)] (standard column i at i, slack of
+ * descending, then index ascending) or Algorithm 8 with diagonal (PRECOND 2) or triangular
+ * (PRECOND 3) expansion (the lowest-indexed row of degree 1 first, columns removed by weight
+ * ascending, then index ascending; the triangular expansion then uses Algorithm 7's order). Column weights w_dev float[nframes*(n+m)] (standard column i at i, slack of
  * check j at n+j). Outputs: pair_dev int32[nframes*m]
  * = column matched to row j (-1 for checks without a cut); lev_b_dev / lev_f_dev
  * int32[nframes*m] = dependency level of row j in the back- and forward-substitution of the

@@ -600,27 +600,37 @@ struct Frame {
     // Fills pair (column of each row), pairrow (row of each chosen standard column), order
     // (rows in elimination order), lfv (forward-substitution level) and lbv
     // (back-substitution level). Returns p.
-    LPD_INLINE int mts(const float *wk)
+    //   With k0 > 0 the search only completes a set: the rows matched so far (order[0..k0),
+    //   their pair, pairrow and lbv) stay, the search runs over the unmatched rows and the
+    //   columns none of whose rows is matched (the matrix A-bar of the triangular expansion
+    //   in Sec. V-B), and its rows follow in order from position k0.
+    LPD_INLINE int mts(const float *wk, int k0 = 0)
     {
         for (int i = tid; i < n; i += nt) {
             int dg = 0;
+            bool excl = false;
             for (int ch = 0; ch < CWC; ++ch) {
                 Ch4 E;
                 ldch(E, clist + (size_t)i * CW + 4 * ch);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) dg += at(E, k) != kEnd;
+                for (int k = 0; k < 4; ++k) {
+                    const uint16_t e = at(E, k);
+                    dg += e != kEnd;
+                    excl |= k0 > 0 && e != kEnd && pair[e_idx(e)] >= 0;
+                }
             }
-            deg[i] = (uint8_t)dg;
-            pairrow[i] = -1;
+            deg[i] = (uint8_t)(excl ? 0 : dg);
+            if (!k0) pairrow[i] = -1;
         }
         int pl = 0;
         for (int j = tid; j < m; j += nt) {
-            pair[j] = -1; lfv[j] = -1; lbv[j] = -1;
-            pl += cut(j);
+            if (!k0) { pair[j] = -1; lbv[j] = -1; }
+            if (pair[j] < 0) { lfv[j] = -1; lbv[j] = -1; }
+            pl += cut(j) && pair[j] < 0;
         }
         for (int k = tid; k < 64 * MW; k += nt) lmask[k] = 0u;
         pl = block_sum1(pl, sc);
-        p = pl;
+        if (!k0) p = pl;
         // rank of each present column among the present columns of its lane
         for (int c = tid; c < n + m; c += nt) {
             if (!present(c)) continue;
@@ -635,7 +645,7 @@ struct Frame {
         }
         __syncthreads();
         for (int c = tid; c < n + m; c += nt)
-            if (present(c) && (c >= n || deg[c] == 1)) mask_set(c, true);
+            if (present(c) && (c >= n ? pair[c - n] < 0 : deg[c] == 1)) mask_set(c, true);
         __syncthreads();
         int done = 0;   // rows eliminated (wave 0)
         if (tid < 64) {
@@ -689,13 +699,13 @@ struct Frame {
                 if (lane == 0) {
                     pair[row] = (int16_t)c;
                     lfv[row] = (int16_t)L;
-                    order[step] = (int16_t)row;
+                    order[k0 + step] = (int16_t)row;
                     if (c < n) pairrow[c] = (int16_t)row;
                     atomicAnd(&lmask[(rkc >> 5) * 64 + (c & 63)], ~(1u << (rkc & 31)));
                     if (c != n + row) atomicAnd(&lmask[(rks >> 5) * 64 + ((n + row) & 63)], ~(1u << (rks & 31)));
                 }
                 // eliminate the row: its waiting columns lose one degree
-                if (ok && i != c && pri < 0) {
+                if (ok && i != c && pri < 0 && dgi >= 0) {
                     deg[i] = (uint8_t)dgi;
                     uint32_t *wp = &lmask[(rki >> 5) * 64 + (i & 63)];
                     if (dgi == 1) atomicOr(wp, 1u << (rki & 31));
@@ -724,13 +734,13 @@ struct Frame {
         if (tid < 64 && done > 0) {
             const int lane = tid;
             const int le = lane < RW ? lane : RW - 1;
-            int rown = order[done - 1];
+            int rown = order[k0 + done - 1];
             uint16_t dn = dep[(size_t)rown * RW + le];
             for (int step = done - 1; step >= 0; --step) {
                 const int row = rown;
                 const uint16_t dd = lane < RW ? dn : kEnd;
                 if (step > 0) {
-                    rown = order[step - 1];
+                    rown = order[k0 + step - 1];
                     dn = dep[(size_t)rown * RW + le];
                 }
                 const int lv = lbv[dd != kEnd ? dd : 0];
@@ -765,7 +775,12 @@ struct Frame {
         const int r = rank[c];
         return (lmask[(r >> 5) * 64 + (c & 63)] >> (r & 31)) & 1u;
     }
-    LPD_INLINE int mts_row(const float *wk)
+    //   With expand = 1 (triangular expansion) the unmatched rows are matched instead by the
+    //   column-wise search over the columns none of whose rows is matched (mts() with k0 =
+    //   the rows matched so far): A_M = [A_M1 0; B A_M2]. Back-substitution levels are then
+    //   walked forward over the row-wise rows and backward over the others (inside mts()),
+    //   forward-substitution levels the other way round.
+    LPD_INLINE int mts_row(const float *wk, int expand = 0)
     {
         const int r1w = (m + 31) >> 5;
         for (int i = tid; i < n; i += nt) {
@@ -871,7 +886,7 @@ struct Frame {
             }
             // diagonal expansion: the unmatched rows with a cut take their slack, ascending
             __builtin_amdgcn_wave_barrier();
-            for (int base = 0; base < m; base += 64) {
+            for (int base = 0; base < m && !expand; base += 64) {
                 const int j = base + lane;
                 const bool un = j < m && cut(j) && pair[j] < 0;
                 const unsigned long long bal = __ballot(un);
@@ -898,21 +913,38 @@ struct Frame {
                 if (lane == 0) lbv[row] = (int16_t)L;
                 __builtin_amdgcn_wave_barrier();
             }
-            for (int step = k - 1; step >= 0; --step) {
-                const int row = order[step], c = pair[row];
-                int L = 0;
-                if (c < n && lane < CW) {
-                    const uint16_t e = clist[(size_t)c * CW + lane];
-                    const int jj = e != kEnd ? e_idx(e) : -1;
-                    L = jj >= 0 && jj != row ? lfv[jj] + 1 : 0;
-                }
-                L = wave_max_t(L);
-                if (lane == 0) lfv[row] = (int16_t)L;
-                __builtin_amdgcn_wave_barrier();
-            }
+            if (!expand) mts_row_fwd_levels(k);
+            if (lane == 0) sc->i[1] = k;
         }
         __syncthreads();
+        if (expand) {
+            const int k1 = sc->i[1];
+            __syncthreads();
+            mts(wk, k1);
+            if (tid < 64) mts_row_fwd_levels(k1);
+            __syncthreads();
+        }
         return pl;
+    }
+
+    // Forward-substitution levels of the first k rows of order, walking backward (their
+    // dependencies, the other rows of the matched column, come later or are already set).
+    // Wave 0.
+    LPD_INLINE void mts_row_fwd_levels(int k)
+    {
+        const int lane = tid & 63;
+        for (int step = k - 1; step >= 0; --step) {
+            const int row = order[step], c = pair[row];
+            int L = 0;
+            if (c < n && lane < CW) {
+                const uint16_t e = clist[(size_t)c * CW + lane];
+                const int jj = e != kEnd ? e_idx(e) : -1;
+                L = jj >= 0 && jj != row ? lfv[jj] + 1 : 0;
+            }
+            L = wave_max_t(L);
+            if (lane == 0) lfv[row] = (int16_t)L;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 
     // The slack columns as preconditioning set (A_M = I): used when Algorithm 7 is off.
@@ -1786,7 +1818,7 @@ struct Frame {
             const bool search = it % o.mts_reuse == 0;
             if (!direct_mode && search) {
                 if (o.precond == 1) mts(nullptr);
-                else if (o.precond == 2) mts_row(nullptr);
+                else if (o.precond == 2 || o.precond == 3) mts_row(nullptr, o.precond - 2);
                 else slack_basis();
                 build_levels();
                 st.max_levels = max(st.max_levels, max(nlb, nlf));

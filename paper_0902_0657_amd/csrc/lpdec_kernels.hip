@@ -93,7 +93,7 @@ LPD_INLINE void run_mts(Frame<PT> &F, const Args &a, int f)
     for (int i = F.tid; i < n; i += F.nt) F.sg[i] = 1;
     __syncthreads();
     F.build_lists();
-    if (a.o.precond == 2) F.mts_row(a.w_in + (size_t)f * (n + m));
+    if (a.o.precond == 2 || a.o.precond == 3) F.mts_row(a.w_in + (size_t)f * (n + m), a.o.precond - 2);
     else F.mts(a.w_in + (size_t)f * (n + m));
     for (int j = F.tid; j < m; j += F.nt) {
         a.i_out[(size_t)f * m + j] = F.pair[j];

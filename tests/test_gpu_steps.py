@@ -99,11 +99,12 @@ def test_mts_irregular_bit_exact(ctx, orc):
         assert np.array_equal(host(lb)[f], lbo) and np.array_equal(host(lf)[f], lfo)
 
 
+@pytest.mark.parametrize("expand", [0, 1])
 @pytest.mark.parametrize("n,kind", [(96, "uniform"), (96, "ties"), (96, "spread"), (1024, "uniform"),
                                     (1024, "ties"), (1024, "spread"), (4096, "spread")])
-def test_mts_rowwise_pairing_and_levels_bit_exact(ctx, orc, n, kind):
-    """Algorithm 8 with diagonal expansion (PRECOND 2): the matched column of every row and
-    both level schedules equal the oracle's."""
+def test_mts_rowwise_pairing_and_levels_bit_exact(ctx, orc, n, kind, expand):
+    """Algorithm 8 with diagonal (PRECOND 2) or triangular (PRECOND 3) expansion: the matched
+    column of every row and both level schedules equal the oracle's."""
     import torch
     code = regular_code(n)
     C = _code(ctx, code)
@@ -112,14 +113,14 @@ def test_mts_rowwise_pairing_and_levels_bit_exact(ctx, orc, n, kind):
     hascut = (rng.random((nf, code.m)) < rng.uniform(0.5, 1.0, (nf, 1))).astype(np.uint8)
     hascut[0] = 1
     W = _weights(rng, nf, code.n + code.m, kind)
-    ctx.set_option("PRECOND", 2)
+    ctx.set_option("PRECOND", 2 + expand)
     try:
         pair, lb, lf, rounds = ctx.mts_batch(C, cuda(hascut, torch.uint8), cuda(W, torch.float32))
     finally:
         ctx.set_option("PRECOND", 1)
     pair, lb, lf = host(pair), host(lb), host(lf)
     for f in range(nf):
-        po, _ = orc.mts_row(code, hascut[f], W[f])
+        po, _ = orc.mts_row(code, hascut[f], W[f], expand=expand)
         lbo, lfo = orc.mts_levels_any(code, hascut[f], po)
         assert np.array_equal(pair[f], po), f
         assert np.array_equal(lb[f], lbo) and np.array_equal(lf[f], lfo), f
