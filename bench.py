@@ -118,11 +118,44 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving(ctx, seconds=10.0, qps=None, seed=5, full=False, streams=None):
-    """Poisson arrivals of frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through
-    lpdec_server (continuous batching over four streams). Latency = submit to result, per
-    request. Default mix: (3,6) n=256 and n=1024; full: also (3,6) n=4096 and the irregular
-    n=8192 code (their fractional frames take tens of seconds each)."""
+def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
+    """Poisson arrivals at qps for `seconds`, then drain. Latency = submit to result."""
+    from synth.channel import awgn_llr, frame_seed
+    t0 = time.perf_counter()
+    tickets, t_next, k = [], t0, 0
+    while time.perf_counter() - t0 < seconds:
+        now = time.perf_counter()
+        while t_next <= now:
+            ci = int(rng.integers(0, len(codes)))
+            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(stream_id, ci, k))
+            tickets.append((srv.submit(Cs[ci], g), codes[ci].n))
+            k += 1
+            t_next += rng.exponential(1.0 / qps)
+        time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
+    srv.drain()
+    wall = time.perf_counter() - t0
+    lat, per, fails = [], {}, []
+    for t, n in tickets:
+        r = srv.poll(t, n)
+        lat.append(r[3])
+        per.setdefault(n, []).append(r[3])
+        if r[1] < 0:
+            fails.append({"n": n, "flag": int(r[1])})
+    lat = np.array(lat)
+    return {"offered_qps": qps, "arrival_s": seconds, "requests": len(lat), "frames_per_s": len(lat) / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "per_code_p50_ms": {str(n): float(np.percentile(v, 50) * 1e3) for n, v in sorted(per.items())},
+            "per_code_p99_ms": {str(n): float(np.percentile(v, 99) * 1e3) for n, v in sorted(per.items())},
+            "numerical_failures": len(fails), "failure_flags": fails}
+
+
+def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None):
+    """Frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through lpdec_server
+    (continuous batching over the context's SERVER_STREAMS streams). First the saturated
+    throughput of the mix (a burst submitted at once, then drained); then Poisson arrivals
+    at a fixed qps and at 0.5x and 0.8x the saturated throughput. Default mix: (3,6) n=256
+    and n=1024; full: also (3,6) n=4096 and the irregular n=8192 code (their fractional
+    frames take seconds to tens of seconds each)."""
     from paper_0902_0657_amd import Code
     from synth.channel import awgn_llr, frame_seed
     from synth.codes import irregular_code, regular_code
@@ -134,35 +167,27 @@ def serving(ctx, seconds=10.0, qps=None, seed=5, full=False, streams=None):
     if streams:
         ctx.set_option("SERVER_STREAMS", streams)
     srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
-    qps = qps or 40.0
-    t0 = time.perf_counter()
-    tickets, t_next, k = [], t0, 0
-    while time.perf_counter() - t0 < seconds:
-        now = time.perf_counter()
-        while t_next <= now:
+    try:
+        burst = 384
+        t0 = time.perf_counter()
+        tk = []
+        for k in range(burst):
             ci = int(rng.integers(0, len(codes)))
-            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(77, ci, k))
-            tickets.append((srv.submit(Cs[ci], g), codes[ci].n))
-            k += 1
-            t_next += rng.exponential(1.0 / qps)
-        time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
-    srv.drain()
-    wall = time.perf_counter() - t0
-    lat, per, fails = [], {}, 0
-    for t, n in tickets:
-        r = srv.poll(t, n)
-        lat.append(r[3])
-        per.setdefault(n, []).append(r[3])
-        fails += r[1] < 0
-    srv.close()
-    lat = np.array(lat)
-    return {"codes": [c.name for c in codes], "requests": len(lat), "offered_qps": qps, "arrival_s": seconds,
-            "streams": int(ctx.get_option("SERVER_STREAMS")),
-            "frames_per_s": len(lat) / wall,
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "per_code_p50_ms": {str(n): float(np.percentile(v, 50) * 1e3) for n, v in sorted(per.items())},
-            "per_code_p99_ms": {str(n): float(np.percentile(v, 99) * 1e3) for n, v in sorted(per.items())},
-            "numerical_failures": int(fails)}
+            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(78, ci, k))
+            tk.append((srv.submit(Cs[ci], g), codes[ci].n))
+        srv.drain()
+        sat = burst / (time.perf_counter() - t0)
+        for t, n in tk:
+            srv.poll(t, n)
+        res = _poisson(srv, Cs, codes, rng, qps, seconds, 77)
+        res.update({"codes": [c.name for c in codes], "streams": int(ctx.get_option("SERVER_STREAMS")),
+                    "saturated_frames_per_s": sat, "burst": burst,
+                    "at_fraction_of_saturated": [dict(fraction=f, **_poisson(srv, Cs, codes, rng, f * sat, seconds,
+                                                                               79 + int(10 * f)))
+                                                 for f in (0.5, 0.8)]})
+    finally:
+        srv.close()
+    return res
 
 
 def sources_digest():
@@ -336,6 +361,10 @@ def main():
         "roofline": primary,
         "roofline_other": secondary,
     }
+    # serving first among the extra legs, while the process holds no other device work
+    if not args.no_serve:
+        res["serving"] = serving(ctx, full=args.serve_full)
+        log(f"serving: {res['serving']['requests']} requests")
     if not args.no_fp32 and fp64:
         c32 = Context(0)
         c32.set_option("PRECISION", 0)
@@ -390,9 +419,6 @@ def main():
                 if not (np.array_equal(xh, xhat[k]) and fl == flags[k]
                         and abs(ob - objs[k]) <= 1e-6 * (1.0 + abs(ob - float(G[k][G[k] < 0].sum()))))]
         res["parity_sample"] = {"frames": len(done), "mismatches": len(mism)}
-    if not args.no_serve:
-        res["serving"] = serving(ctx, full=args.serve_full)
-        log(f"serving: {res['serving']['requests']} requests")
     print(json.dumps(res))
 
 

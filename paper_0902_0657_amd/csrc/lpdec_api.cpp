@@ -516,8 +516,8 @@ extern "C" lpdec_status lpdec_ipm_batch(lpdec_ctx *ctx, const lpdec_code *code, 
 
 // ------------------------------------------------------------------------------ serving
 // Continuous batching. Submitted frames wait in a host queue. A scheduler thread forms a
-// wave from the queue head whenever one of its streams is idle: it takes frames (of one code
-// per wave) while the wave's device footprint fits in the free part of the HBM budget and
+// wave whenever one of its streams is idle: the queue head and the later queued frames of
+// the same code, while the wave's device footprint fits in the free part of the HBM budget and
 // the slots in flight stay under max_slots, copies their gamma to the wave's device buffer,
 // launches the decode kernel on that stream and records an event. Waves on different
 // streams overlap on the device. Each frame's results go to host-mapped pinned memory with a
@@ -668,18 +668,23 @@ void server_loop(lpdec_server *s)
             s->slots_in_use -= freed_slots;
             for (auto &L : s->lanes) {
                 if (L.busy || s->queue.empty()) continue;
+                // the head request and every later queued request of the same code, in
+                // arrival order, while the budget and the slots allow; the others keep their
+                // places
                 const lpdec_code *code = s->queue.front().code;
                 const size_t fp = frame_footprint(code, pt64);
                 int nf = 0;
                 size_t need = 0;
-                for (auto it = s->queue.begin(); it != s->queue.end() && it->code == code; ++it) {
+                for (auto it = s->queue.begin(); it != s->queue.end();) {
+                    if (it->code != code) { ++it; continue; }
                     if (s->slots_in_use + nf + 1 > s->max_slots) break;
                     if (s->in_use + need + fp > s->budget) break;
                     need += fp;
                     ++nf;
+                    L.wave.push_back(std::move(*it));
+                    it = s->queue.erase(it);
                 }
                 if (nf == 0) break;
-                for (int k = 0; k < nf; ++k) { L.wave.push_back(std::move(s->queue.front())); s->queue.pop_front(); }
                 s->in_use += need;
                 s->slots_in_use += nf;
                 L.busy = true;

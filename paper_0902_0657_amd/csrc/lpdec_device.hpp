@@ -1654,10 +1654,11 @@ struct Frame {
         block_exscan(ridx, m);
         const int P = ridx[m], Pp = (P + T - 1) / T * T;
         double *const Q = qd;
-        {
-            double2 *const q2 = (double2 *)Q;
-            const size_t n2 = (size_t)Pp * Pp / 2;
-            for (size_t t2 = tid; t2 < n2; t2 += nt) q2[t2] = make_double2(0.0, 0.0);
+        // zero the tiles on and below the diagonal (the only ones read), a wave per row
+        for (int rr = tid >> 6; rr < Pp; rr += nt >> 6) {
+            double2 *const q2 = (double2 *)(Q + (size_t)rr * Pp);
+            const int w2 = ((rr / T) + 1) * (T / 2);
+            for (int c2 = tid & 63; c2 < w2; c2 += 64) q2[c2] = make_double2(0.0, 0.0);
         }
         __syncthreads();
         // lower triangle, one thread per LP row: row r gets a_ri a_r'i d_i^2 for every column i
