@@ -1446,6 +1446,18 @@ struct Frame {
 #pragma unroll
             for (int c = 0; c < T; ++c) ldsd[c * T + r] = a[c];
         }
+        // forward substitution of this block (L y = colk, fused into the factorisation): the
+        // rows below were already reduced by the earlier panels
+        double v = colk[K + r];
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+            const double xc = lp_readlane_d(v, c) * lp_readlane_d(a[c], c);
+            v = r == c ? xc : (r > c ? v - a[c] * xc : v);
+        }
+        if (lane < T) {
+            colk[K + r] = v;
+            ldsd[T * T + T + r] = v;
+        }
     }
 
     // Rows below the diagonal tile: row i becomes x with x L_KK^T = a_i, one thread per row,
@@ -1475,6 +1487,15 @@ struct Frame {
             }
 #pragma unroll
             for (int c = 0; c < T; c += 2) *(double2 *)(row + c) = make_double2(a[c], a[c + 1]);
+            // the fused forward substitution: this row's right-hand side loses L_iK y_K
+            const double *const yk = ldsd + T * T + T;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < T; c += 2) {
+                s0 += a[c] * yk[o0 + c];
+                s1 += a[c + 1] * yk[o0 + c + 1];
+            }
+            colk[i] -= s0 + s1;
         }
     }
 
@@ -1561,7 +1582,8 @@ struct Frame {
         }
     }
 
-    // Cholesky factor of the padded Q in place (lower triangle), block column by block column.
+    // Cholesky factor of the padded Q in place (lower triangle), block column by block column,
+    // with the forward substitution L y = colk carried along (colk becomes y).
     LPD_INLINE void dense_factor(double *Q, int Pp, double dm)
     {
         constexpr int T = kDenseTile;
@@ -1575,46 +1597,14 @@ struct Frame {
         }
     }
 
-    // L y = colk, then L^T x = y, in place in colk (Pp entries) by blocks of T rows: wave 0
-    // solves the diagonal block in registers, the workgroup updates the other rows. The
-    // diagonal of Q holds the reciprocals of L's diagonal.
+    // L^T x = y in place in colk (Pp entries; y comes from the forward substitution fused
+    // into dense_factor) by blocks of T rows: wave 0 solves the diagonal block in registers,
+    // the workgroup updates the other rows. The diagonal of Q holds the reciprocals of L's
+    // diagonal.
     LPD_INLINE void dense_subst(const double *Q, int Pp)
     {
         constexpr int T = kDenseTile;
         double *const xs = ldsd + T * T + T;
-        for (int K = 0; K < Pp; K += T) {
-            if (tid < 64) {
-                const int lane = tid, r = lane & (T - 1);
-                const double *const row = Q + (size_t)(K + r) * Pp + K;
-                double a[T];
-#pragma unroll
-                for (int c = 0; c < T; c += 2) {
-                    const double2 v = *(const double2 *)(row + c);
-                    a[c] = v.x;
-                    a[c + 1] = v.y;
-                }
-                double v = colk[K + r];
-#pragma unroll
-                for (int c = 0; c < T; ++c) {
-                    const double xc = lp_readlane_d(v, c) * lp_readlane_d(a[c], c);
-                    v = lane == c ? xc : (lane > c ? v - a[c] * xc : v);
-                }
-                if (lane < T) { colk[K + r] = v; xs[r] = v; }
-            }
-            __syncthreads();
-            for (int i = K + T + tid; i < Pp; i += nt) {
-                const double *const row = Q + (size_t)i * Pp + K;
-                double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int c = 0; c < T; c += 2) {
-                    const double2 v = *(const double2 *)(row + c);
-                    s0 += v.x * xs[c];
-                    s1 += v.y * xs[c + 1];
-                }
-                colk[i] -= s0 + s1;
-            }
-            __syncthreads();
-        }
         for (int K = Pp - T; K >= 0; K -= T) {
             if (tid < 64) {
                 const int lane = tid, r = lane & (T - 1);
@@ -1687,13 +1677,13 @@ struct Frame {
             dm = fmax(dm, diag);
         }
         for (int r = P + tid; r < Pp; r += nt) Q[(size_t)r * Pp + r] = 1.0;
-        dm = block_max_d(dm, sc);
-        dense_factor(Q, Pp, dm);
-        // L y = w, then L^T x = y, in colk (indexed by LP row; the padding rows are zero)
+        // right-hand side in colk, indexed by LP row (the padding rows are zero): the
+        // factorisation also runs the forward substitution L y = w, then L^T x = y
         for (int j = tid; j < m; j += nt)
             if (cut(j)) colk[ridx[j]] = w[j];
         for (int r = P + tid; r < Pp; r += nt) colk[r] = 0.0;
-        __syncthreads();
+        dm = block_max_d(dm, sc);
+        dense_factor(Q, Pp, dm);
         dense_subst(Q, Pp);
         for (int j = tid; j < m; j += nt)
             if (cut(j)) dy[j] = colk[ridx[j]];
