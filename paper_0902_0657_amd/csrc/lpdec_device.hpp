@@ -1433,7 +1433,10 @@ struct Frame {
             colbuf[c * T + r] = a[c];
             double s = colbuf[c * T + c];
             if (!(s > 1e-30 * dm)) s = 1e128;
-            const double lcc = sqrt(s), inv = 1.0 / lcc;
+            // 1/sqrt(s): the hardware estimate refined by two Newton steps y (3 - s y^2) / 2
+            double inv = __builtin_amdgcn_rsq(s);
+            inv = inv * (1.5 - 0.5 * s * inv * inv);
+            inv = inv * (1.5 - 0.5 * s * inv * inv);
             a[c] = r == c ? inv : (r > c ? a[c] * inv : a[c]);
             ldsd[T * T + c] = inv;
             const double lrc = a[c];
@@ -1605,12 +1608,18 @@ struct Frame {
     {
         constexpr int T = kDenseTile;
         double *const xs = ldsd + T * T + T;
+        const int r = tid & (T - 1);
+        double bn[T];   // wave 0: column r of the next diagonal block, loaded one block ahead
+        if (tid < 64 && Pp >= T) {
+#pragma unroll
+            for (int c = 0; c < T; ++c) bn[c] = Q[(size_t)(Pp - T + c) * Pp + Pp - T + r];
+        }
         for (int K = Pp - T; K >= 0; K -= T) {
             if (tid < 64) {
-                const int lane = tid, r = lane & (T - 1);
+                const int lane = tid;
                 double bc[T];   // bc[c] = L[K + c][K + r]
 #pragma unroll
-                for (int c = 0; c < T; ++c) bc[c] = Q[(size_t)(K + c) * Pp + K + r];
+                for (int c = 0; c < T; ++c) bc[c] = bn[c];
                 double v = colk[K + r];
 #pragma unroll
                 for (int c = T - 1; c >= 0; --c) {
@@ -1620,6 +1629,10 @@ struct Frame {
                 if (lane < T) { colk[K + r] = v; xs[r] = v; }
             }
             __syncthreads();
+            if (tid < 64 && K >= T) {
+#pragma unroll
+                for (int c = 0; c < T; ++c) bn[c] = Q[(size_t)(K - T + c) * Pp + K - T + r];
+            }
             for (int j = tid; j < K; j += nt) {
                 double s0 = 0.0, s1 = 0.0;
 #pragma unroll
