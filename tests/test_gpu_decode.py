@@ -258,3 +258,27 @@ def test_dense_fallback_path(ctx, orc, block):
     s = stats_table(st)
     assert np.all(s["direct_solves"][s["malp_iters"] > 0] > 0)
     _compare(orc, code, G, out)
+
+
+def test_autotune_block(ctx, orc, tmp_path):
+    """The launch-shape tuner times each candidate, keeps the fastest in the context and in its
+    cache file, and the tuned context still decodes like the oracle."""
+    import torch
+    from paper_0902_0657_amd import autotune
+    code = regular_code(96)
+    C = _code(ctx, code)
+    G = batch_awgn(code.n, 0.5, 2.0, 16, stream=21)
+    g = cuda(G, torch.float64)
+    cache = str(tmp_path / "tune.json")
+    autotune._CACHE.clear()
+    try:
+        rec = autotune.tune_block(ctx, C, g, candidates=(64, 128), cache_file=cache)
+        assert rec["block"] in (64, 128) and set(rec["ms"]) == {64, 128}
+        assert int(ctx.get_option("BLOCK")) == rec["block"]
+        assert os.path.exists(cache)
+        out = ctx.decode_batch(C, g)
+        torch.cuda.synchronize()
+        _compare(orc, code, G, out)
+    finally:
+        ctx.set_option("BLOCK", 0)
+        autotune._CACHE.clear()
