@@ -190,6 +190,100 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None):
     return res
 
 
+def precond_study(seed=606):
+    """The comparison of Sec. VI-B on a synthetic (3,6) n=2000 code: Newton systems of the IPM
+    at its 8th and 18th iteration, in the 6th LP of an MALP-A decode, once for a frame decoded
+    integral at 1.5 dB and once for a fractional one at 1.0 dB. For each preconditioner the
+    relative residual ||w - Q y||^2 / ||w||^2 of FP64 PCG after k iterations (one round, no
+    refinement). The systems come from the library itself: the cut set from the decode trace,
+    the IPM point from lpdec_ipm_batch stopped after 7 and 17 iterations; w is assembled here
+    from that point by the formulas of Sec. IV-B."""
+    import torch
+    from paper_0902_0657_amd import Code, Context
+    from synth.channel import batch_awgn
+    from synth.codes import regular_code
+    dev = torch.device("cuda:0")
+    code = regular_code(2000)
+    n, m = code.n, code.m
+    H = code.dense().astype(np.float64)
+    ctx = Context(0)
+    ctx.set_option("PRECISION", 1)
+    C = Code.from_synth(ctx, code)
+    names = {4: "CG (no preconditioner)", 0: "slack columns (diagonal)", 1: "Algorithm 7 (column-wise)",
+             2: "Algorithm 8 (row-wise, diagonal expansion)", 3: "Algorithm 8 (row-wise, triangular expansion)"}
+    steps = (5, 10, 20, 40, 80, 120, 160, 200)
+    systems = []
+    for label, snr, want in (("integral, 1.5 dB", 1.5, 1), ("fractional, 1.0 dB", 1.0, 0)):
+        G = batch_awgn(n, 0.5, snr, 64, stream=seed + int(10 * snr))
+        g = torch.as_tensor(G, device=dev)
+        tr = ctx.decode_batch_trace(C, g, trace_cap=8)
+        torch.cuda.synchronize()
+        flag = tr["flag"].cpu().numpy()
+        malp = tr["stats"].cpu().numpy()[:, 0]
+        cand = [f for f in range(G.shape[0]) if flag[f] == want and malp[f] >= 6]
+        if not cand:
+            continue
+        f = min(cand, key=lambda k: (abs(int(malp[k]) - 6), k))
+        vm = tr["trace"].cpu().numpy()[f, 5].astype(np.uint32)
+        gam = G[f].astype(np.float64)
+        sg = np.where(gam >= 0, 1.0, -1.0)
+        rows = np.nonzero(vm)[0]
+        p = len(rows)
+        # the augmented LP of Sec. IV-B: A = [A_std | I_p], b, c = (|gamma|, 0)
+        A = np.zeros((p, n + p))
+        b = np.zeros(p)
+        for r, j in enumerate(rows):
+            cols = np.nonzero(H[j])[0]
+            sv = np.array([1.0 if (int(vm[j]) >> k) & 1 else -1.0 for k in range(len(cols))])
+            A[r, cols] = sg[cols] * sv
+            A[r, n + r] = 1.0
+            b[r] = (sv > 0).sum() - 1 - sv[sg[cols] < 0].sum()
+        c = np.concatenate([np.abs(gam), np.zeros(p)])
+        for it in (8, 18):
+            ctx.set_option("IPM_MAX", it - 1)
+            vmd = torch.as_tensor(vm[None, :].view(np.int32).copy(), device=dev)
+            x, y, z, its, status = ctx.ipm_batch(C, vmd, torch.as_tensor(gam[None, :], device=dev), precision=1)
+            ctx.set_option("IPM_MAX", 100)
+            x, y, z = x.cpu().numpy()[0], y.cpu().numpy()[0], z.cpu().numpy()[0]
+            idx = np.concatenate([np.arange(n), n + rows])
+            xa, za, ya = x[idx], z[idx], y[rows]
+            d2 = xa / za
+            mu = 0.1 * float(xa @ za) / (n + p)
+            rb = b - A @ xa
+            rc = c - A.T @ ya - za
+            re = mu - xa * za
+            w = rb + A @ (d2 * rc) - A @ (re / za)
+            Q = (A * d2) @ A.T
+            ev = np.linalg.eigvalsh(Q)
+            d2full = np.zeros(n + m)
+            d2full[:n] = d2[:n]
+            d2full[n + rows] = d2[n:]
+            wfull = np.zeros(m)
+            wfull[rows] = w
+            sysrec = {"system": label, "frame": int(f), "malp_iterations": int(malp[f]), "ipm_iteration": it,
+                      "rows": p, "columns": n + p, "duality_gap": float(xa @ za), "kappa": float(ev[-1] / ev[0]),
+                      "residual2": {}}
+            for pc in (4, 0, 1, 2, 3):
+                ctx.set_option("PRECOND", pc)
+                ctx.set_option("REF_MAX", 0)
+                ctx.set_option("PCG_TOL", 1e-30)
+                curve = []
+                for k in steps:
+                    ctx.set_option("PCG_MAXIT", k)
+                    _, itn, res = ctx.newton_solve_batch(
+                        C, vmd, torch.as_tensor(gam[None, :], device=dev), torch.as_tensor(d2full[None, :], device=dev),
+                        torch.as_tensor(wfull[None, :], device=dev), precision=1)
+                    curve.append([k, float(res.cpu().numpy()[0]) ** 2])
+                sysrec["residual2"][names[pc]] = curve
+            for key, v in (("PRECOND", 1), ("REF_MAX", 3), ("PCG_TOL", 1e-6), ("PCG_MAXIT", 0)):
+                ctx.set_option(key, v)
+            systems.append(sysrec)
+            log(f"precond study: {label}, IPM iteration {it}, p = {p}")
+    ctx.close()
+    return {"precond_study": {"code": "(3,6)-regular n=2000, 4-cycle free", "lp": "6th MALP-A iteration",
+                              "metric": "||w - Q y||^2 / ||w||^2 after k FP64 PCG iterations", "systems": systems}}
+
+
 def sources_digest():
     """SHA-256 over the HIP sources and the C header: identifies the kernel build that a
     stored traffic measurement belongs to."""
@@ -255,6 +349,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB copy first (HBM counter calibration under rocprofv3)")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--precond-study", action="store_true",
+                    help="print the preconditioner comparison of Sec. VI-B (n=2000 code) instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: frames are independent LPs and the "
@@ -262,6 +358,9 @@ def main():
                                    "run with --gpus 1"}))
         sys.exit(2)
 
+    if args.precond_study:
+        print(json.dumps(precond_study()))
+        return
     import torch
     from paper_0902_0657_amd import Code, Context, _lib, stats_table
     if not os.path.exists(_lib.LIB_PATH):

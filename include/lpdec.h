@@ -114,7 +114,8 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  default), 2 = from Algorithm 8 (row-wise greedy, diagonal expansion),
  *                  3 = Algorithm 8 with triangular expansion (the unmatched rows by the
  *                  column-wise greedy over the columns of unmatched rows only), 0 = the slack
- *                  columns as preconditioning set (a diagonal preconditioner)
+ *                  columns as preconditioning set (a diagonal preconditioner), 4 = no
+ *                  preconditioner (plain CG on A D^2 A^T in FP64, the baseline of Sec. VI-B)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
  *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
@@ -195,7 +196,7 @@ lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int3
                                     double *lhs_dev);
 
 /* The triangular-set search of the context's PRECOND on the LP whose rows are the checks
- * with hascut_dev[f*m+j] != 0: Algorithm 7 (PRECOND 1 or 0; columns ordered by weight
+ * with hascut_dev[f*m+j] != 0: Algorithm 7 (PRECOND 0, 1 or 4; columns ordered by weight
  * descending, then index ascending) or Algorithm 8 with diagonal (PRECOND 2) or triangular
  * (PRECOND 3) expansion (the lowest-indexed row of degree 1 first, columns removed by weight
  * ascending, then index ascending; the triangular expansion then uses Algorithm 7's order). Column weights w_dev float[nframes*(n+m)] (standard column i at i, slack of

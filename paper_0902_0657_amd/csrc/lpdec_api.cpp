@@ -232,7 +232,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
         if (!(v == 0 || (ipos(64) && v <= 256 && ((int)v % 64) == 0))) break;
         ctx->block = (int)v;
         return LPDEC_OK;
-    case LPDEC_OPT_PRECOND: if (v != 0 && v != 1 && v != 2 && v != 3) break; o.precond = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_PRECOND: if (!(ipos(0) && v <= 4)) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_STREAMS: if (!ipos(1) || v > 32) break; ctx->server_streams = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
     case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;

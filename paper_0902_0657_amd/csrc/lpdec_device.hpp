@@ -947,6 +947,15 @@ struct Frame {
         }
     }
 
+    // The preconditioning set of the context's PRECOND from the weights d2f: Algorithm 7 (1),
+    // Algorithm 8 with diagonal (2) or triangular (3) expansion, else the slack columns.
+    LPD_INLINE void find_precond_set()
+    {
+        if (o.precond == 1) mts(nullptr);
+        else if (o.precond == 2 || o.precond == 3) mts_row(nullptr, o.precond - 2);
+        else slack_basis();
+    }
+
     // The slack columns as preconditioning set (A_M = I): used when Algorithm 7 is off.
     LPD_INLINE void slack_basis()
     {
@@ -1318,6 +1327,68 @@ struct Frame {
         return block_sum1(nr2, sc);
     }
 
+    // Algorithm 4 without a preconditioner (M = I), in FP64, on the current residual rho: the
+    // CG baseline of the comparison in Sec. VI-B (PRECOND 4). Stops at ||r|| <= tol ||rho||,
+    // at the round's cap or when h^T Q h <= 0; adds the correction to dy. Returns the
+    // iterations.
+    LPD_INLINE int plain_cg_round(double tol)
+    {
+        double *const r = c64[0], *const h = c64[1], *const l = c64[2], *const xv = c64[3];
+        double rr = 0.0;
+        for (int j = tid; j < m; j += nt) {
+            const double rj = cut(j) ? rho[j] : 0.0;
+            r[j] = rj;
+            h[j] = rj;
+            xv[j] = 0.0;
+            rr += rj * rj;
+        }
+        rr = block_sum1(rr, sc);
+        const double stop = tol * tol * rr;
+        const int maxit = pcg_cap();
+        int it = 0;
+        while (it < maxit && rr > 0.0) {
+            // l = A D^2 A^T h
+            for (int i = tid; i < n; i += nt) tq[i] = d2[i] * col_dot<double>(i, h);
+            __syncthreads();
+            double hl = 0.0;
+            for (int j = tid; j < m; j += nt) {
+                if (!cut(j)) continue;
+                double acc = d2[n + j] * h[j];
+                for (int ch = 0; ch < RWC; ++ch) {
+                    Ch8 E;
+                    ldch(E, rlist + (size_t)j * RW + 8 * ch);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc += sgather<double>(at(E, k), tq);
+                }
+                l[j] = acc;
+                hl += h[j] * acc;
+            }
+            hl = block_sum1(hl, sc);
+            if (!(hl > 0.0)) break;
+            const double alpha = rr / hl;
+            double rr2 = 0.0;
+            for (int j = tid; j < m; j += nt) {
+                if (!cut(j)) continue;
+                xv[j] += alpha * h[j];
+                const double rj = r[j] - alpha * l[j];
+                r[j] = rj;
+                rr2 += rj * rj;
+            }
+            rr2 = block_sum1(rr2, sc);
+            ++it;
+            if (rr2 <= stop) break;
+            const double beta = rr2 / rr;
+            rr = rr2;
+            for (int j = tid; j < m; j += nt)
+                if (cut(j)) h[j] = r[j] + beta * h[j];
+            __syncthreads();
+        }
+        for (int j = tid; j < m; j += nt)
+            if (cut(j)) dy[j] += xv[j];
+        __syncthreads();
+        return it;
+    }
+
     // Newton solve (A D^2 A^T) dy = w: rounds of PCG on the current FP64 residual rho,
     // dy += correction, rho = w - Q dy recomputed in FP64 (iterative refinement).
     // Inside the interior-point method (mu > 0) a round is good enough once the
@@ -1368,7 +1439,8 @@ struct Frame {
         int its = 0, wide = sizeof(PT) == 8, left = o.ref_max;
         double prev = use_xi ? 1e300 : nw2;
         for (int rd = 0;; ++rd) {
-            its += wide && sizeof(PT) != 8 ? cg_round<double>(V2, tol2, xs) : cg_round<PT>(V1, tol1, xs);
+            its += o.precond == 4 ? plain_cg_round(tol2)
+                                  : (wide && sizeof(PT) != 8 ? cg_round<double>(V2, tol2, xs) : cg_round<PT>(V1, tol1, xs));
             double nr2 = residual64();
             double err = use_xi ? xi_max() : nr2;
             if (!(err < prev)) {
@@ -1821,9 +1893,7 @@ struct Frame {
             const long long t0 = wall_clock64();
             const bool search = it % o.mts_reuse == 0;
             if (!direct_mode && search) {
-                if (o.precond == 1) mts(nullptr);
-                else if (o.precond == 2 || o.precond == 3) mts_row(nullptr, o.precond - 2);
-                else slack_basis();
+                find_precond_set();
                 build_levels();
                 st.max_levels = max(st.max_levels, max(nlb, nlf));
             }

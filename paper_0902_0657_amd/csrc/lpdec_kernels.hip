@@ -51,8 +51,7 @@ LPD_INLINE void run_solve(Frame<PT> &F, const Args &a, int f)
     }
     __syncthreads();
     F.build_lists();
-    if (F.o.precond) F.mts(nullptr);
-    else F.slack_basis();
+    F.find_precond_set();
     F.build_levels();
     int refr = 0, escal = 0;
     double resid2 = 0.0;
