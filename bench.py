@@ -434,7 +434,7 @@ def main():
                                "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
                                + ("FP64 PCG" if fp64 else "FP32 PCG") + " (Algorithm 4, Algorithm 7 "
                                "preconditioner) with FP64 refinement first; once PCG misses its goal within "
-                               "the automatic cap (about p^2/7000 iterations) the LP's remaining Newton systems "
+                               "the automatic cap (max(100, p^2/3500) iterations, one round) the LP's remaining Newton systems "
                                "go to dense FP64 Cholesky on the matrix cores",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),

@@ -1256,16 +1256,19 @@ struct Frame {
         return it;
     }
 
-    // PCG iteration cap of one round. PCG_MAXIT > 0 is used as given; 0 (automatic) bounds a
-    // round by what the dense fallback would cost for this LP when the fallback exists (its
-    // work grows as p^3: about 160 iterations at p = 470), else 500.
+    // PCG iteration cap of one round. PCG_MAXIT > 0 is used as given; 0 (automatic) gives a
+    // PCG attempt at least 100 iterations, which is enough for the early IPM systems of
+    // every LP, and for large LPs about twice the cost of the dense fallback (one dense solve
+    // costs about p^2 / 7000 PCG iterations: its work grows as p^3, a PCG iteration's as p);
+    // 500 without the fallback. Inside the IPM a round that reaches the cap hands the system
+    // to the dense solve.
     LPD_INLINE int pcg_cap() const
     {
         if (o.pcg_maxit > 0) return o.pcg_maxit;
         if (!qd) return 500;
         const double pp = (double)p;
-        const double cap = pp * pp / 7000.0;
-        return cap < 20.0 ? 20 : (cap > 2000.0 ? 2000 : (int)cap);
+        const double cap = pp * pp / 3500.0;
+        return cap < 100.0 ? 100 : (cap > 2000.0 ? 2000 : (int)cap);
     }
 
     // One refinement round in precision T: r = L^-1 rho, PCG, dy += L^-T v (transforms in
@@ -1438,9 +1441,11 @@ struct Frame {
         const double xs = use_xi ? xi_goal : 0.0;
         int its = 0, wide = sizeof(PT) == 8, left = o.ref_max;
         double prev = use_xi ? 1e300 : nw2;
+        const int cap = pcg_cap();
         for (int rd = 0;; ++rd) {
-            its += o.precond == 4 ? plain_cg_round(tol2)
-                                  : (wide && sizeof(PT) != 8 ? cg_round<double>(V2, tol2, xs) : cg_round<PT>(V1, tol1, xs));
+            const int ri = o.precond == 4 ? plain_cg_round(tol2)
+                                          : (wide && sizeof(PT) != 8 ? cg_round<double>(V2, tol2, xs) : cg_round<PT>(V1, tol1, xs));
+            its += ri;
             double nr2 = residual64();
             double err = use_xi ? xi_max() : nr2;
             if (!(err < prev)) {
@@ -1456,6 +1461,9 @@ struct Frame {
                                      : (nr2 <= o.ref_tol * o.ref_tol * nw2);
             met = done;
             if (done || !(err == err)) break;
+            // a round that ran into the cap inside the IPM hands the system to the dense
+            // solve, when there is one: refinement only pays after a PCG round that converged
+            if (use_xi && qd && ri >= cap) break;
             if (!wide && (err > (use_xi ? 0.5 : 0.25) * prev || left <= 0)) {
                 wide = 1;
                 ++escal;
