@@ -10,7 +10,8 @@ Prints one JSON line. Extra legs, each reported beside the main number:
                pointers), a bounded sample;
   cpu_baseline the FP64 CPU oracle on the host cores, a time-bounded sample;
   roofline     effective bandwidth of the decode kernel on its algorithmic bytes;
-  serving      (--serve) Poisson arrivals of mixed-length frames through lpdec_server.
+  serving      Poisson arrivals of mixed-length frames through lpdec_server (persistent
+               engines, then the wave scheduler as serving_waves).
 """
 from __future__ import annotations
 
@@ -149,9 +150,10 @@ def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
             "numerical_failures": len(fails), "failure_flags": fails}
 
 
-def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None):
+def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1):
     """Frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through lpdec_server
-    (continuous batching over the context's SERVER_STREAMS streams). First the saturated
+    (mode 0: continuous batching over the context's SERVER_STREAMS streams; mode 1: a
+    persistent kernel per code that takes each request as a workgroup frees). First the saturated
     throughput of the mix (a burst submitted at once, then drained); then Poisson arrivals
     at a fixed qps and at 0.5x and 0.8x the saturated throughput. Default mix: (3,6) n=256
     and n=1024; full: also (3,6) n=4096 and the irregular n=8192 code (their fractional
@@ -166,7 +168,10 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None):
     rng = np.random.Generator(np.random.PCG64(seed))
     if streams:
         ctx.set_option("SERVER_STREAMS", streams)
+    prev = ctx.get_option("SERVER_MODE")
+    ctx.set_option("SERVER_MODE", mode)
     srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
+    ctx.set_option("SERVER_MODE", prev)
     try:
         burst = 384
         t0 = time.perf_counter()
@@ -179,8 +184,11 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None):
         sat = burst / (time.perf_counter() - t0)
         for t, n in tk:
             srv.poll(t, n)
+        log(f"serving mode {mode}: burst of {burst} at {sat:.0f} frames/s")
         res = _poisson(srv, Cs, codes, rng, qps, seconds, 77)
-        res.update({"codes": [c.name for c in codes], "streams": int(ctx.get_option("SERVER_STREAMS")),
+        log(f"serving mode {mode}: {qps:.0f} qps p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+        res.update({"mode": "persistent" if mode else "waves", "codes": [c.name for c in codes],
+                    "streams": int(ctx.get_option("SERVER_STREAMS")) if mode == 0 else len(codes),
                     "saturated_frames_per_s": sat, "burst": burst,
                     "at_fraction_of_saturated": [dict(fraction=f, **_poisson(srv, Cs, codes, rng, f * sat, seconds,
                                                                                79 + int(10 * f)))
@@ -462,8 +470,10 @@ def main():
     }
     # serving first among the extra legs, while the process holds no other device work
     if not args.no_serve:
-        res["serving"] = serving(ctx, full=args.serve_full)
+        res["serving"] = serving(ctx, full=args.serve_full, mode=1)
         log(f"serving: {res['serving']['requests']} requests")
+        res["serving_waves"] = serving(ctx, full=args.serve_full, mode=0)
+        log(f"serving (waves): {res['serving_waves']['requests']} requests")
     if not args.no_fp32 and fp64:
         c32 = Context(0)
         c32.set_option("PRECISION", 0)

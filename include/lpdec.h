@@ -141,6 +141,17 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   SERVER_STREAMS HIP streams (waves in flight) of a server created afterwards (1..32, 8).
  *                  Streams beyond the process's hardware queues (HIP's GPU_MAX_HW_QUEUES,
  *                  4 unless set before HIP starts) share queues and their waves serialize
+ *   SERVER_MODE    scheduling of a server created afterwards. 0 = waves: a stream (of
+ *                  SERVER_STREAMS) takes every queued request of the head's code and launches
+ *                  one workgroup per frame; a new wave starts when a stream's previous wave
+ *                  has ended. 1 (default) = persistent: each code gets an engine, a kernel of up to
+ *                  min(max_slots, CUs) workgroups (fewer if the budget is short) that stays
+ *                  resident and takes the next request as soon as a workgroup is free; the
+ *                  compute units are shared evenly among the engines that have requests, and
+ *                  a kernel leaves after about 5 ms in which no request was decoded or waiting
+ *                  and is launched again on the next one. An engine holds its
+ *                  workspace until the server is destroyed or its budget is needed by another
+ *                  code's engine while it has no work. Results are bit-identical to mode 0
  */
 enum {
     LPDEC_OPT_MALP_MODE = 0, LPDEC_OPT_PRECISION, LPDEC_OPT_TAU_VIOL, LPDEC_OPT_TAU_ACT,
@@ -148,7 +159,7 @@ enum {
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
     LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT_MTS_REUSE, LPDEC_OPT_WARM_START,
-    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT__COUNT
+    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT_SERVER_MODE, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);

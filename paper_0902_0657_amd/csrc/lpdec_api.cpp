@@ -61,6 +61,7 @@ struct lpdec_ctx {
     int precision = -1;   // -1: per call default
     int block = 0;        // 0: automatic
     int server_streams = 8;
+    int server_mode = 1;
     int lds_limit = 65536;
     std::string err;
     Workspace ws;
@@ -143,7 +144,8 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     a.code = view(code);
     a.o = ctx->opts;
     // the dense fallback exists only inside the IPM (decode and IPM modes)
-    const bool dense = ctx->opts.direct && (a.mode == lpdec::MODE_DECODE || a.mode == lpdec::MODE_IPM);
+    const bool dense = ctx->opts.direct && (a.mode == lpdec::MODE_DECODE || a.mode == lpdec::MODE_IPM ||
+                                            a.mode == lpdec::MODE_SERVE);
     a.plan = lpdec::make_plan(code->m, code->n, code->dcmax, code->dvmax, pt64 ? 8 : 4, dense);
     const size_t lds_dense = a.plan.dense_on ? lpdec::kDenseLdsBytes : 0;
     const size_t lds_need = lpdec::lp_align(a.plan.hot_bytes) + lds_dense;
@@ -234,6 +236,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
         return LPDEC_OK;
     case LPDEC_OPT_PRECOND: if (!(ipos(0) && v <= 4)) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_STREAMS: if (!ipos(1) || v > 32) break; ctx->server_streams = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_SERVER_MODE: if (v != 0 && v != 1) break; ctx->server_mode = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
     case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;
     case LPDEC_OPT_DIRECT_FALLBACK: if (v != 0 && v != 1) break; o.direct = (int)v; return LPDEC_OK;
@@ -267,6 +270,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_BLOCK: *v = ctx->block; break;
     case LPDEC_OPT_PRECOND: *v = o.precond; break;
     case LPDEC_OPT_SERVER_STREAMS: *v = ctx->server_streams; break;
+    case LPDEC_OPT_SERVER_MODE: *v = ctx->server_mode; break;
     case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
     case LPDEC_OPT_IPM_STALL: *v = o.eps_stall; break;
     case LPDEC_OPT_DIRECT_FALLBACK: *v = o.direct; break;
@@ -579,6 +583,30 @@ struct Lane {
     bool busy = false;
 };
 
+// Persistent engine of one code (server mode 1): a kernel of W workgroups that claim tickets
+// from a ring of R request slots in host-mapped memory, each slot holding the frame's LLRs and
+// its results. Device ticket t uses slot t mod R; the host publishes t only once the slot's
+// previous ticket has been retired.
+struct Engine {
+    const lpdec_code *code = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ended = nullptr;
+    Workspace ws;                 // kernel workspace of the W workgroups
+    int32_t *claim = nullptr;     // device: tickets claimed so far
+    HostOut ring;                 // gamma | xhat | flag | obj | done per slot, then published,
+                                  // stop, share
+    int R = 0, W = 0;
+    size_t off_x = 0, off_f = 0, off_o = 0, off_d = 0, off_c = 0;
+    int32_t published = 0;        // tickets published (the host's copy of the ring counter)
+    std::vector<Request> slot;    // the request each used slot holds
+    std::vector<char> used;
+    std::deque<Request> backlog;  // taken from the queue, waiting for their slot
+    int outstanding = 0;          // published and not yet retired
+    bool running = false;
+    size_t footprint = 0;
+    int32_t *ctl() const { return (int32_t *)(ring.h + off_c); }
+};
+
 }  // namespace
 
 struct lpdec_server {
@@ -592,6 +620,9 @@ struct lpdec_server {
     std::map<uint64_t, int> pending;   // ticket -> 1 while queued or running
     uint64_t next_ticket = 1;
     std::vector<Lane> lanes;
+    int mode = 0;                                  // 0: waves on streams; 1: persistent engines
+    std::vector<std::unique_ptr<Engine>> engines;  // mode 1, owned by the server thread
+    int ncu = 0;
     size_t in_use = 0;
     int slots_in_use = 0;
     bool stop = false;
@@ -759,6 +790,268 @@ void server_loop(lpdec_server *s)
     }
 }
 
+// ------------------------------------------------------------------ persistent engines
+// Server mode 1. Each code gets an Engine once a request for it arrives; the engine's kernel
+// stays resident while requests keep coming and leaves after about 5 ms in which none was
+// decoded or waiting (or when the engine is freed), and the server thread launches it again when tickets wait and it has left.
+// The thread alone touches the engines and, in this mode, the budget counter in_use.
+
+constexpr int kIdlePolls = 100;   // about 5 ms
+
+hipError_t engine_init(Engine &E, const lpdec_code *code, int W, int R)
+{
+    using lpdec::lp_align;
+    E.code = code;
+    E.W = W;
+    E.R = R;
+    const size_t n = (size_t)code->n;
+    E.off_x = lp_align(8 * (size_t)R * n);
+    E.off_f = E.off_x + lp_align((size_t)R * n);
+    E.off_o = E.off_f + lp_align(4 * (size_t)R);
+    E.off_d = E.off_o + lp_align(8 * (size_t)R);
+    E.off_c = E.off_d + lp_align(4 * (size_t)R);
+    E.slot.resize(R);
+    E.used.assign(R, 0);
+    hipError_t e = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ended, hipEventDisableTiming);
+    if (e == hipSuccess) e = hostout_ensure(E.ring, E.off_c + 256);
+    if (e == hipSuccess) std::memset(E.ring.h, 0, E.ring.bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&E.claim, 256);
+    if (e == hipSuccess) e = hipMemset(E.claim, 0, 256);
+    return e;
+}
+
+// Asks a resident kernel to leave, waits for it, and frees everything the engine holds.
+void engine_free(Engine &E)
+{
+    if (E.ring.h) __atomic_store_n(E.ctl() + 1, 1, __ATOMIC_RELEASE);
+    if (E.stream) (void)hipStreamSynchronize(E.stream);
+    ws_free(E.ws);
+    if (E.claim) (void)hipFree(E.claim);
+    if (E.ring.h) (void)hipHostFree(E.ring.h);
+    if (E.ended) (void)hipEventDestroy(E.ended);
+    if (E.stream) (void)hipStreamDestroy(E.stream);
+    E.claim = nullptr;
+    E.ring = HostOut{};
+    E.ended = nullptr;
+    E.stream = nullptr;
+}
+
+lpdec_status engine_launch(lpdec_server *s, Engine &E, int pt64)
+{
+    Args a{};
+    a.mode = lpdec::MODE_SERVE;
+    a.gamma = E.ring.d;
+    a.gamma_f64 = 1;
+    a.xhat = (uint8_t *)(E.ring.d + E.off_x);
+    a.flag = (int32_t *)(E.ring.d + E.off_f);
+    a.obj = (double *)(E.ring.d + E.off_o);
+    a.done = (int32_t *)(E.ring.d + E.off_d);
+    a.claim = E.claim;
+    a.published = (const int32_t *)(E.ring.d + E.off_c);
+    a.stop = (const int32_t *)(E.ring.d + E.off_c) + 1;
+    a.share = (const int32_t *)(E.ring.d + E.off_c) + 2;
+    // workgroups beyond the current share would leave at once
+    a.nframes = std::max(1, std::min(E.W, E.ctl()[2]));
+    a.ring = E.R;
+    a.idle_polls = kIdlePolls;
+    // the previous launch on this stream has ended: it left no ticket held and closed itself
+    // (or stopped); clear its busy count and closing flag
+    if (hipMemsetAsync(E.claim + 1, 0, 8, E.stream) != hipSuccess) return LPDEC_EDEVICE;
+    lpdec_status st = launch(s->ctx, E.code, a, pt64, E.ws, E.stream);
+    if (st == LPDEC_OK && hipEventRecord(E.ended, E.stream) != hipSuccess) st = LPDEC_EDEVICE;
+    if (st == LPDEC_OK) E.running = true;
+    return st;
+}
+
+// The engine of a code, created if the budget allows (engines without work are freed first
+// when it does not); null if the request has to wait. hip_failed reports an engine that could
+// not be set up.
+Engine *engine_for(lpdec_server *s, const lpdec_code *code, int pt64, bool &hip_failed)
+{
+    hip_failed = false;
+    for (auto &E : s->engines)
+        if (E->code == code) return E.get();
+    const size_t fp = frame_footprint(code, pt64);
+    const int want = std::min(s->max_slots, s->ncu);
+    auto room = [&] { return (long long)((s->budget - s->in_use) / fp); };
+    if (room() < want) {
+        for (size_t k = 0; k < s->engines.size();) {
+            Engine &E = *s->engines[k];
+            if (E.outstanding || !E.backlog.empty()) { ++k; continue; }
+            engine_free(E);
+            s->in_use -= E.footprint;
+            s->engines.erase(s->engines.begin() + (long)k);
+        }
+    }
+    const int W = (int)std::min<long long>(want, room());
+    if (W < 1) return nullptr;
+    auto E = std::make_unique<Engine>();
+    const int R = std::max(64, std::min(4096, 2 * s->max_slots));
+    if (engine_init(*E, code, W, R) != hipSuccess) {
+        engine_free(*E);
+        hip_failed = true;
+        return nullptr;
+    }
+    E->footprint = (size_t)W * fp;
+    s->in_use += E->footprint;
+    s->engines.push_back(std::move(E));
+    return s->engines.back().get();
+}
+
+void server_loop_persistent(lpdec_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    const int pt64 = precision_for(s->ctx, 1);
+    auto failed = [](const Request &r) {
+        Result res;
+        res.xhat.assign(r.code->n, 0);
+        res.flag = LPDEC_FLAG_NONFINITE;
+        return std::make_pair(r.ticket, std::move(res));
+    };
+    std::vector<std::pair<uint64_t, Result>> done;
+    while (true) {
+        // retire the frames whose done flags are set; an engine whose kernel has ended is
+        // marked idle before its flags are read, so that a ticket still without a flag then was
+        // published after the workgroups left and waits for the next launch
+        int freed = 0;
+        const auto now = std::chrono::steady_clock::now();
+        for (auto &Ep : s->engines) {
+            Engine &E = *Ep;
+            if (E.running && hipEventQuery(E.ended) != hipErrorNotReady) E.running = false;
+            if (!E.outstanding) continue;
+            const int n = E.code->n;
+            const volatile int32_t *dn = (const volatile int32_t *)(E.ring.h + E.off_d);
+            for (int k = 0; k < E.R; ++k) {
+                if (!E.used[k] || !dn[k]) continue;
+                std::atomic_thread_fence(std::memory_order_acquire);
+                Result r;
+                const uint8_t *xh = (const uint8_t *)E.ring.h + E.off_x + (size_t)k * n;
+                r.xhat.assign(xh, xh + n);
+                r.flag = ((const volatile int32_t *)(E.ring.h + E.off_f))[k];
+                r.obj = ((const volatile double *)(E.ring.h + E.off_o))[k];
+                r.latency = std::chrono::duration<double>(now - E.slot[k].t_submit).count();
+                done.emplace_back(E.slot[k].ticket, std::move(r));
+                E.slot[k] = Request{};
+                E.used[k] = 0;
+                --E.outstanding;
+                ++freed;
+            }
+        }
+        // admission: queued requests in arrival order while slots are left
+        std::vector<Request> incoming;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &d : done) {
+                s->results[d.first] = std::move(d.second);
+                s->pending.erase(d.first);
+            }
+            s->slots_in_use -= freed;
+            while (!s->queue.empty() && s->slots_in_use < s->max_slots) {
+                incoming.push_back(std::move(s->queue.front()));
+                s->queue.pop_front();
+                ++s->slots_in_use;
+            }
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+        done.clear();
+        size_t k = 0;
+        for (; k < incoming.size(); ++k) {
+            bool hip_failed = false;
+            Engine *E = engine_for(s, incoming[k].code, pt64, hip_failed);
+            if (hip_failed) {
+                done.push_back(failed(incoming[k]));
+                continue;
+            }
+            if (!E) break;
+            E->backlog.push_back(std::move(incoming[k]));
+        }
+        if (k < incoming.size() || !done.empty()) {
+            // requests that wait for budget go back to the head of the queue in their order
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t j = incoming.size(); j-- > k;) s->queue.push_front(std::move(incoming[j]));
+            s->slots_in_use -= (int)(incoming.size() - k);
+            for (auto &d : done) {
+                s->results[d.first] = std::move(d.second);
+                s->pending.erase(d.first);
+            }
+            s->slots_in_use -= (int)done.size();
+            if (!done.empty()) s->err = "engine setup failed";
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+        done.clear();
+        // publish into free slots
+        bool busy = false;
+        int active = 0;
+        for (auto &Ep : s->engines) {
+            Engine &E = *Ep;
+            if (!E.running && !E.outstanding && E.published > (1 << 30)) {
+                // restart the ticket counters long before they could overflow
+                E.published = 0;
+                __atomic_store_n(E.ctl(), 0, __ATOMIC_RELEASE);
+                if (hipMemset(E.claim, 0, 256) != hipSuccess) s->err = "engine counter reset failed";
+            }
+            const size_t n = (size_t)E.code->n;
+            bool pub = false;
+            while (!E.backlog.empty()) {
+                const int k = E.published % E.R;
+                if (E.used[k]) break;
+                Request &r = E.backlog.front();
+                std::memcpy(E.ring.h + 8 * (size_t)k * n, r.gamma.data(), 8 * n);
+                ((volatile int32_t *)(E.ring.h + E.off_d))[k] = 0;
+                E.slot[k] = std::move(r);
+                E.backlog.pop_front();
+                E.used[k] = 1;
+                ++E.outstanding;
+                ++E.published;
+                pub = true;
+            }
+            if (pub) __atomic_store_n(E.ctl(), E.published, __ATOMIC_RELEASE);
+            active += E.outstanding > 0 || !E.backlog.empty();
+        }
+        // the compute units are shared evenly among the engines with work (one workgroup per
+        // compute unit each); an engine without work keeps its workgroups only while no other
+        // has any. Then launch an engine whose kernel has left while tickets wait.
+        for (auto &Ep : s->engines) {
+            Engine &E = *Ep;
+            const bool work = E.outstanding > 0 || !E.backlog.empty();
+            const int share = work ? std::max(1, s->ncu / std::max(1, active)) : (active ? 0 : s->ncu);
+            if (E.ctl()[2] != share) __atomic_store_n(E.ctl() + 2, share, __ATOMIC_RELAXED);
+            if (!E.running && E.outstanding > 0 && engine_launch(s, E, pt64) != LPDEC_OK) {
+                for (int j = 0; j < E.R; ++j) {
+                    if (!E.used[j]) continue;
+                    done.push_back(failed(E.slot[j]));
+                    E.slot[j] = Request{};
+                    E.used[j] = 0;
+                }
+                E.outstanding = 0;
+                // the device never saw these tickets: count them as claimed
+                (void)hipMemcpy(E.claim, &E.published, 4, hipMemcpyHostToDevice);
+            }
+            busy |= E.outstanding > 0 || !E.backlog.empty();
+        }
+        if (!done.empty()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &d : done) {
+                s->results[d.first] = std::move(d.second);
+                s->pending.erase(d.first);
+            }
+            s->slots_in_use -= (int)done.size();
+            s->err = "engine launch failed";
+            s->cv_done.notify_all();
+            done.clear();
+        }
+        if (busy) {
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            continue;
+        }
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop && s->queue.empty()) break;
+        s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        if (s->stop && s->queue.empty()) break;
+    }
+}
+
 }  // namespace
 
 extern "C" lpdec_status lpdec_server_create(lpdec_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots,
@@ -772,6 +1065,16 @@ extern "C" lpdec_status lpdec_server_create(lpdec_ctx *ctx, size_t hbm_budget_by
     s->ctx = ctx;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
+    s->mode = ctx->server_mode;
+    if (s->mode == 1) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || ncu < 1)
+            ncu = 1;
+        s->ncu = ncu;
+        s->worker = std::thread(server_loop_persistent, s);
+        *out = s;
+        return LPDEC_OK;
+    }
     s->lanes.resize(ctx->server_streams);
     for (auto &L : s->lanes) {
         if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -838,6 +1141,7 @@ extern "C" lpdec_status lpdec_server_destroy(lpdec_server *s)
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    for (auto &E : s->engines) engine_free(*E);
     for (auto &L : s->lanes) {
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         ws_free(L.ws);

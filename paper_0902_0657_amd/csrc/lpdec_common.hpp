@@ -160,6 +160,7 @@ enum Mode : int {
     MODE_MATVEC = 3,      // l = A D^2 A^T h
     MODE_MTS = 4,         // Algorithm 7 + levels
     MODE_CUTS = 5,        // Algorithm 2 on every check
+    MODE_SERVE = 6,       // persistent: frames claimed from a host ring until idle or stopped
 };
 
 // Kernel arguments (one struct, passed by value).
@@ -187,6 +188,18 @@ struct Args {
     double *obj;               // [nframes]
     int32_t *done;             // [nframes], nullable: set to 1 once the frame's outputs are
                                // visible to the host (outputs in host-mapped memory)
+    // MODE_SERVE: frames are ring slots; ticket t (claimed once, in order, from claim[0] while
+    // t < *published) is slot t mod ring. claim[1] counts the workgroups holding or claiming a
+    // ticket; claim[2] closes the launch: set by a workgroup that has polled idle_polls times
+    // in a row (about 54 us apart) while no ticket was held or unclaimed, it makes every
+    // workgroup leave. A workgroup also leaves when *stop is set or its index is not below
+    // *share
+    int32_t *claim;            // device memory, claim[1] and claim[2] zero at launch
+    const int32_t *published;  // host-mapped
+    const int32_t *stop;       // host-mapped
+    const int32_t *share;      // host-mapped
+    int ring;
+    int idle_polls;
     lpdec_stats *stats;        // [nframes]
     double *u_out;             // [nframes*n]
     uint32_t *trace;           // [nframes*trace_cap*m]

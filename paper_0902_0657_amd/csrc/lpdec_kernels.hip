@@ -118,6 +118,69 @@ LPD_INLINE void run_cuts(Frame<PT> &F, const Args &a, int f)
     }
 }
 
+// Persistent serving loop: thread 0 claims the next published ticket (compare-and-swap on a
+// device counter, so every ticket is decoded exactly once and only after the host published
+// it), the workgroup decodes that ring slot, and repeats. Without a ticket it sleeps and polls.
+// The launch ends as a whole: once a workgroup has polled idle_polls times in a row while no
+// workgroup held a ticket and none was unclaimed, it closes the launch and every workgroup
+// leaves, so
+// that a launch never goes on with only a few of its workgroups while requests come in.
+// Between frames a workgroup also leaves when the host sets stop, or lowers the engine's share
+// of workgroups below its index (so that another code's engine gets the compute unit). Tickets
+// published after the launch closed stay unclaimed for the next launch.
+template <typename PT>
+LPD_INLINE void run_serve(Frame<PT> &F, const Args &a)
+{
+    int32_t *const busy = a.claim + 1, *const closing = a.claim + 2;
+    constexpr int R = __ATOMIC_RELAXED;
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT, SY = __HIP_MEMORY_SCOPE_SYSTEM;
+    for (;;) {
+        __syncthreads();   // the previous frame's last reads of the scratch area are done
+        if (F.tid == 0) {
+            int got = -1;
+            for (int polls = 0;; ++polls) {
+                // relaxed polls: a system-scope acquire invalidates caches, and hundreds of
+                // idle workgroups doing so every poll slow down the ones that decode; the one
+                // acquire is taken after a successful claim
+                if (__hip_atomic_load(a.stop, R, SY) || __hip_atomic_load(closing, R, AG)) break;
+                if ((int)blockIdx.x >= __hip_atomic_load(a.share, R, SY)) break;
+                const int pub = __hip_atomic_load(a.published, R, SY);
+                int c = __hip_atomic_load(a.claim, R, AG);
+                if (c < pub) {
+                    // counted as busy before the claim, so that no workgroup closes the launch
+                    // between this claim and its frame
+                    __hip_atomic_fetch_add(busy, 1, R, AG);
+                    if (__hip_atomic_compare_exchange_strong(a.claim, &c, c + 1, R, R, AG)) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the slot's LLRs
+                        got = c;
+                        break;
+                    }
+                    __hip_atomic_fetch_add(busy, -1, R, AG);
+                    continue;
+                }
+                // idle_polls polls in a row with no workgroup holding a ticket
+                if (__hip_atomic_load(busy, R, AG) != 0) {
+                    polls = -1;
+                } else if (polls >= a.idle_polls) {
+                    int zero = 0;
+                    (void)__hip_atomic_compare_exchange_strong(closing, &zero, 1, R, R, AG);
+                    break;
+                }
+                // 16 x 127 x 64 clocks (about 54 us at 2.4 GHz) between polls of the
+                // host-mapped counter
+                for (int k = 0; k < 16; ++k) __builtin_amdgcn_s_sleep(127);
+            }
+            F.sc->i[2] = got;
+        }
+        __syncthreads();
+        const int t = F.sc->i[2];
+        __syncthreads();
+        if (t < 0) return;
+        F.decode(a, t % a.ring);
+        if (F.tid == 0) __hip_atomic_fetch_add(busy, -1, R, AG);
+    }
+}
+
 template <typename PT, bool HOT_LDS, int MODE>
 __global__ void __launch_bounds__(256) lpdec_main(Args a)
 {
@@ -137,6 +200,7 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
     else if constexpr (MODE == MODE_MATVEC) run_matvec(F, a, f);
     else if constexpr (MODE == MODE_MTS) run_mts(F, a, f);
     else if constexpr (MODE == MODE_CUTS) run_cuts(F, a, f);
+    else if constexpr (MODE == MODE_SERVE) run_serve(F, a);
 }
 
 size_t static_lds_bytes() { return sizeof(Scratch); }
@@ -168,6 +232,7 @@ static hipError_t launch_m(const Args &a, int block, size_t lds_bytes, hipStream
     case MODE_MATVEC: return launch_t<PT, HOT_LDS, MODE_MATVEC>(a, block, lds_bytes, stream);
     case MODE_MTS: return launch_t<PT, HOT_LDS, MODE_MTS>(a, block, lds_bytes, stream);
     case MODE_CUTS: return launch_t<PT, HOT_LDS, MODE_CUTS>(a, block, lds_bytes, stream);
+    case MODE_SERVE: return launch_t<PT, HOT_LDS, MODE_SERVE>(a, block, lds_bytes, stream);
     default: return hipErrorInvalidValue;
     }
 }
