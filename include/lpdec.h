@@ -185,7 +185,10 @@ lpdec_status lpdec_decode(lpdec_ctx *ctx, const lpdec_code *code, const double *
  * obj_dev double[nframes] (nullable); stats_dev lpdec_stats[nframes] (nullable);
  * u_dev double[nframes*n] (nullable). Workspace is owned by the context and reused; a
  * second call on the same context may start only after the first has finished on the
- * device, unless both use the same stream. */
+ * device, unless both use the same stream. A batch with more frames than the device has
+ * compute units is decoded hardest-first: four small kernels on `stream` order the frames by
+ * descending syndrome weight of their hard decisions (scratch in the workspace), and the
+ * decode takes them in that order. Outputs stay indexed by frame and do not depend on it. */
 lpdec_status lpdec_decode_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
                                 const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
                                 int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,

@@ -63,6 +63,7 @@ struct lpdec_ctx {
     int server_streams = 8;
     int server_mode = 1;
     int lds_limit = 65536;
+    int ncu = 256;        // compute units of the device
     std::string err;
     Workspace ws;
 };
@@ -154,10 +155,23 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     a.hot_stride = a.hot_in_lds ? 0 : lpdec::lp_align(a.plan.hot_bytes + 255) & ~(size_t)255;
     a.cold_stride = (a.plan.cold_bytes + 255) & ~(size_t)255;
     const size_t per = a.hot_stride + a.cold_stride;
-    hipError_t e = ws_ensure(ws, per * (size_t)a.nframes);
+    // a decode batch with more frames than the device holds at once starts its likely-slowest
+    // frames first (the order, weights and histogram follow the frames' arenas)
+    const bool ordered = a.mode == lpdec::MODE_DECODE && a.nframes > ctx->ncu;
+    const size_t nf4 = lpdec::lp_align(4 * (size_t)a.nframes);
+    const size_t extra = ordered ? 2 * nf4 + lpdec::lp_align(4 * ((size_t)code->m + 1)) : 0;
+    hipError_t e = ws_ensure(ws, per * (size_t)a.nframes + extra);
     if (e != hipSuccess) return hipfail(ctx, e, "workspace allocation");
     a.cold_ws = ws.ptr;
     a.hot_ws = ws.ptr + a.cold_stride * (size_t)a.nframes;
+    a.order = nullptr;
+    if (ordered) {
+        char *base = ws.ptr + per * (size_t)a.nframes;
+        int32_t *order = (int32_t *)base, *w = (int32_t *)(base + nf4), *hist = (int32_t *)(base + 2 * nf4);
+        e = lpdec::launch_order(a, order, w, hist, stream);
+        if (e != hipSuccess) return hipfail(ctx, e, "order launch");
+        a.order = order;
+    }
     int block = ctx->block > 0 ? ctx->block : auto_block(code);
     e = lpdec::launch_main(a, pt64, block, a.hot_in_lds ? lds_need : lds_dense, stream);
     if (e != hipSuccess) return hipfail(ctx, e, "kernel launch");
@@ -191,9 +205,11 @@ extern "C" lpdec_status lpdec_ctx_create(int device, lpdec_ctx **out)
     if (!c) return LPDEC_ENOMEM;
     c->device = device;
     default_opts(c->opts);
-    int lds = 0;
+    int lds = 0, ncu = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->lds_limit = lds;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->ncu = ncu;
     *out = c;
     return LPDEC_OK;
 }
@@ -985,11 +1001,12 @@ void server_loop_persistent(lpdec_server *s)
         int active = 0;
         for (auto &Ep : s->engines) {
             Engine &E = *Ep;
-            if (!E.running && !E.outstanding && E.published > (1 << 30)) {
-                // restart the ticket counters long before they could overflow
+            if (!E.running && !E.outstanding && E.published > (1 << 30) &&
+                hipMemset(E.claim, 0, 256) == hipSuccess) {
+                // restart the ticket counters long before they could overflow (the device
+                // counter first; if that fails both keep counting)
                 E.published = 0;
                 __atomic_store_n(E.ctl(), 0, __ATOMIC_RELEASE);
-                if (hipMemset(E.claim, 0, 256) != hipSuccess) s->err = "engine counter reset failed";
             }
             const size_t n = (size_t)E.code->n;
             bool pub = false;

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
     F.bind(a, hot, cold, &sc);
     // tiles of the dense fallback follow the hot arena in dynamic LDS
     F.ldsd = a.plan.dense_on ? (double *)(lds_dyn + (HOT_LDS ? lp_align(a.plan.hot_bytes) : 0)) : nullptr;
-    if constexpr (MODE == MODE_DECODE) F.decode(a, f);
+    if constexpr (MODE == MODE_DECODE) F.decode(a, a.order ? a.order[f] : f);
     else if constexpr (MODE == MODE_IPM) run_ipm(F, a, f);
     else if constexpr (MODE == MODE_SOLVE) run_solve(F, a, f);
     else if constexpr (MODE == MODE_MATVEC) run_matvec(F, a, f);
@@ -204,6 +204,90 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
 }
 
 size_t static_lds_bytes() { return sizeof(Scratch); }
+
+// ---------------------------------------------------------------- dispatch order of a batch
+// A launch lasts as long as its slowest workgroup chain: a hard frame whose workgroup is
+// dispatched only after the first wave of frames has finished extends it. The decode therefore
+// takes the frames by descending syndrome weight of their hard decisions (the number of checks
+// the channel decisions violate), which tracks the number of cuts and LPs a frame needs. The
+// order decides only which workgroup decodes a frame and when; every frame's result is the same.
+
+__global__ void __launch_bounds__(256) order_clear(int32_t *hist, int nbins)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbins) hist[i] = 0;
+}
+
+// one thread per frame: syndrome weight and its histogram
+__global__ void __launch_bounds__(256) order_weights(Args a, int32_t *w, int32_t *hist)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.nframes) return;
+    const CodeView &cd = a.code;
+    const size_t off = (size_t)f * cd.n;
+    int wt = 0;
+    for (int j = 0; j < cd.m; ++j) {
+        int par = 0;
+        for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) {
+            const size_t k = off + cd.col[e];
+            const double g = a.gamma_f64 ? ((const double *)a.gamma)[k] : (double)((const float *)a.gamma)[k];
+            par ^= g < 0.0 ? 1 : 0;
+        }
+        wt += par;
+    }
+    w[f] = wt;
+    atomicAdd(&hist[wt], 1);
+}
+
+// one workgroup: hist[v] becomes the number of frames of weight above v (the first position of
+// weight v in the order)
+__global__ void __launch_bounds__(256) order_bases(int32_t *hist, int nbins)
+{
+    __shared__ int part[256];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int chunk = (nbins + nt - 1) / nt;
+    // thread t owns bins top - t*chunk down to top - (t+1)*chunk + 1 (descending weights)
+    const int hi = nbins - 1 - t * chunk, lo = max(hi - chunk + 1, 0);
+    int sum = 0;
+    for (int v = hi; v >= lo; --v) sum += hist[v];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < nt; ++k) {
+            const int c = part[k];
+            part[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    int run = part[t];
+    for (int v = hi; v >= lo; --v) {
+        const int c = hist[v];
+        hist[v] = run;
+        run += c;
+    }
+}
+
+// one thread per frame: its position; frames of equal weight take their places in any order
+__global__ void __launch_bounds__(256) order_scatter(int nframes, const int32_t *w, int32_t *hist, int32_t *order)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nframes) return;
+    order[atomicAdd(&hist[w[f]], 1)] = f;
+}
+
+hipError_t launch_order(const Args &a, int32_t *order, int32_t *w, int32_t *hist, hipStream_t stream)
+{
+    (void)hipGetLastError();
+    const int nbins = a.code.m + 1;
+    const int gf = (a.nframes + 255) / 256, gb = (nbins + 255) / 256;
+    hipLaunchKernelGGL(order_clear, dim3(gb), dim3(256), 0, stream, hist, nbins);
+    hipLaunchKernelGGL(order_weights, dim3(gf), dim3(256), 0, stream, a, w, hist);
+    hipLaunchKernelGGL(order_bases, dim3(1), dim3(256), 0, stream, hist, nbins);
+    hipLaunchKernelGGL(order_scatter, dim3(gf), dim3(256), 0, stream, a.nframes, (const int32_t *)w, hist, order);
+    return hipGetLastError();
+}
 
 template <typename PT, bool HOT_LDS, int MODE>
 static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream_t stream)

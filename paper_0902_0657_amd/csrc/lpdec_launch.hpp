@@ -11,5 +11,9 @@ namespace lpdec {
 hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream);
 // Static LDS used by the kernel besides the hot arena.
 size_t static_lds_bytes();
+// Dispatch order of a decode batch (a.nframes frames of a.gamma): order[0..nframes) lists the
+// frames by descending syndrome weight of their hard decisions. w holds nframes and hist
+// m + 1 ints of scratch.
+hipError_t launch_order(const Args &a, int32_t *order, int32_t *w, int32_t *hist, hipStream_t stream);
 
 }  // namespace lpdec
