@@ -218,15 +218,14 @@ __global__ void __launch_bounds__(256) order_clear(int32_t *hist, int nbins)
     if (i < nbins) hist[i] = 0;
 }
 
-// one thread per frame: syndrome weight and its histogram
-__global__ void __launch_bounds__(256) order_weights(Args a, int32_t *w, int32_t *hist)
+// one wave per frame: syndrome weight (lanes take checks in turn) and its histogram
+__global__ void __launch_bounds__(64) order_weights(Args a, int32_t *w, int32_t *hist)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= a.nframes) return;
+    const int f = blockIdx.x, lane = threadIdx.x;
     const CodeView &cd = a.code;
     const size_t off = (size_t)f * cd.n;
     int wt = 0;
-    for (int j = 0; j < cd.m; ++j) {
+    for (int j = lane; j < cd.m; j += 64) {
         int par = 0;
         for (int e = cd.rowptr[j]; e < cd.rowptr[j + 1]; ++e) {
             const size_t k = off + cd.col[e];
@@ -235,8 +234,11 @@ __global__ void __launch_bounds__(256) order_weights(Args a, int32_t *w, int32_t
         }
         wt += par;
     }
-    w[f] = wt;
-    atomicAdd(&hist[wt], 1);
+    for (int d = 32; d > 0; d >>= 1) wt += __shfl_xor(wt, d, 64);
+    if (lane == 0) {
+        w[f] = wt;
+        atomicAdd(&hist[wt], 1);
+    }
 }
 
 // one workgroup: hist[v] becomes the number of frames of weight above v (the first position of
@@ -269,23 +271,41 @@ __global__ void __launch_bounds__(256) order_bases(int32_t *hist, int nbins)
     }
 }
 
-// one thread per frame: its position; frames of equal weight take their places in any order
+// one workgroup: each frame's position, frames of equal weight in index order. Chunks of 256
+// frames in turn; a frame's rank among the equal-weight frames before it in the chunk is counted
+// in LDS, and the chunk's last frame of each weight advances that weight's next position.
 __global__ void __launch_bounds__(256) order_scatter(int nframes, const int32_t *w, int32_t *hist, int32_t *order)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nframes) return;
-    order[atomicAdd(&hist[w[f]], 1)] = f;
+    __shared__ int wl[256];
+    const int t = threadIdx.x;
+    for (int c0 = 0; c0 < nframes; c0 += 256) {
+        const int f = c0 + t;
+        const int wf = f < nframes ? w[f] : -1;
+        wl[t] = wf;
+        __syncthreads();
+        int rank = 0;
+        bool last = true;
+        if (wf >= 0) {
+            for (int k = 0; k < t; ++k) rank += wl[k] == wf ? 1 : 0;
+            for (int k = t + 1; k < 256; ++k)
+                if (wl[k] == wf) { last = false; break; }
+            order[hist[wf] + rank] = f;
+        }
+        __syncthreads();   // every frame of the chunk has read its weight's position
+        if (wf >= 0 && last) hist[wf] += rank + 1;
+        __syncthreads();
+    }
 }
 
 hipError_t launch_order(const Args &a, int32_t *order, int32_t *w, int32_t *hist, hipStream_t stream)
 {
     (void)hipGetLastError();
     const int nbins = a.code.m + 1;
-    const int gf = (a.nframes + 255) / 256, gb = (nbins + 255) / 256;
+    const int gb = (nbins + 255) / 256;
     hipLaunchKernelGGL(order_clear, dim3(gb), dim3(256), 0, stream, hist, nbins);
-    hipLaunchKernelGGL(order_weights, dim3(gf), dim3(256), 0, stream, a, w, hist);
+    hipLaunchKernelGGL(order_weights, dim3(a.nframes), dim3(64), 0, stream, a, w, hist);
     hipLaunchKernelGGL(order_bases, dim3(1), dim3(256), 0, stream, hist, nbins);
-    hipLaunchKernelGGL(order_scatter, dim3(gf), dim3(256), 0, stream, a.nframes, (const int32_t *)w, hist, order);
+    hipLaunchKernelGGL(order_scatter, dim3(1), dim3(256), 0, stream, a.nframes, (const int32_t *)w, hist, order);
     return hipGetLastError();
 }
 
