@@ -1,7 +1,6 @@
 """Benchmark: LP-decoded frames/s of the batched decoder on the (3,6)-regular n=1024 code.
 
-One step = one lpdec_decode_batch call (a dispatch-order pre-pass of four small kernels, under
-1 ms, then one launch of the decoder) over a batch of 512 frames (Eb/N0 1.5 / 2.0 / 2.5 dB,
+One step = one launch of the decoder over a batch of 512 frames (Eb/N0 1.5 / 2.0 / 2.5 dB,
 171/171/170 frames, FP32 LLRs, FP64 PCG with the dense FP64 fallback): every step of the hot path
 (cut search, cut update, interior-point iterations, triangular-set search, PCG) runs inside
 that launch. Inputs are resident in device memory before timing starts.

@@ -152,6 +152,9 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  and is launched again on the next one. An engine holds its
  *                  workspace until the server is destroyed or its budget is needed by another
  *                  code's engine while it has no work. Results are bit-identical to mode 0
+ *   DISPATCH_ORDER 1 (default) = a decode batch larger than the device holds at once takes
+ *                  its frames hardest-first (see lpdec_decode_batch); 0 = in index order.
+ *                  Results do not depend on it
  */
 enum {
     LPDEC_OPT_MALP_MODE = 0, LPDEC_OPT_PRECISION, LPDEC_OPT_TAU_VIOL, LPDEC_OPT_TAU_ACT,
@@ -159,7 +162,8 @@ enum {
     LPDEC_OPT_PCG_MAXIT, LPDEC_OPT_REF_TOL, LPDEC_OPT_REF_MAX, LPDEC_OPT_IPM_MAX,
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
     LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT_MTS_REUSE, LPDEC_OPT_WARM_START,
-    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT_SERVER_MODE, LPDEC_OPT__COUNT
+    LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT_SERVER_MODE,
+    LPDEC_OPT_DISPATCH_ORDER, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);
@@ -185,10 +189,12 @@ lpdec_status lpdec_decode(lpdec_ctx *ctx, const lpdec_code *code, const double *
  * obj_dev double[nframes] (nullable); stats_dev lpdec_stats[nframes] (nullable);
  * u_dev double[nframes*n] (nullable). Workspace is owned by the context and reused; a
  * second call on the same context may start only after the first has finished on the
- * device, unless both use the same stream. A batch with more frames than the device has
- * compute units is decoded hardest-first: four small kernels on `stream` order the frames by
- * descending syndrome weight of their hard decisions (scratch in the workspace), and the
- * decode takes them in that order. Outputs stay indexed by frame and do not depend on it. */
+ * device, unless both use the same stream. A batch with more frames than the device holds at
+ * once (workgroups per compute unit x compute units) is launched as one resident set of
+ * workgroups that take the frames in turn from a counter in the workspace. With
+ * DISPATCH_ORDER 1 (default) they take them hardest-first: four small kernels on `stream`
+ * first order the frames by descending syndrome weight of their hard decisions. Outputs stay
+ * indexed by frame and do not depend on either. */
 lpdec_status lpdec_decode_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
                                 const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
                                 int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,

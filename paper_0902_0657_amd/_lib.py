@@ -13,7 +13,7 @@ FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT = -1, -2, -3, -4
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",
-    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL", "DIRECT_FALLBACK", "MTS_REUSE", "WARM_START", "SERVER_STREAMS", "IPM_WARM", "SERVER_MODE"])}
+    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL", "DIRECT_FALLBACK", "MTS_REUSE", "WARM_START", "SERVER_STREAMS", "IPM_WARM", "SERVER_MODE", "DISPATCH_ORDER"])}
 
 
 class Stats(C.Structure):

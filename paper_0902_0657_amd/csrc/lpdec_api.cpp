@@ -64,6 +64,7 @@ struct lpdec_ctx {
     int server_mode = 1;
     int lds_limit = 65536;
     int ncu = 256;        // compute units of the device
+    int dispatch_order = 1;
     std::string err;
     Workspace ws;
 };
@@ -155,25 +156,40 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
     a.hot_stride = a.hot_in_lds ? 0 : lpdec::lp_align(a.plan.hot_bytes + 255) & ~(size_t)255;
     a.cold_stride = (a.plan.cold_bytes + 255) & ~(size_t)255;
     const size_t per = a.hot_stride + a.cold_stride;
-    // a decode batch with more frames than the device holds at once starts its likely-slowest
-    // frames first (the order, weights and histogram follow the frames' arenas)
-    const bool ordered = a.mode == lpdec::MODE_DECODE && a.nframes > ctx->ncu;
+    const int block = ctx->block > 0 ? ctx->block : auto_block(code);
+    const size_t lds_launch = a.hot_in_lds ? lds_need : lds_dense;
+    // a decode batch larger than the device holds at once runs as one resident set of
+    // workgroups that take the frames in turn (hardest first with DISPATCH_ORDER 1); the
+    // counter, order, weights and histogram follow the workgroups' arenas
+    int grid = a.nframes;
+    if (a.mode == lpdec::MODE_DECODE) {
+        const long long cap = (long long)lpdec::decode_per_cu(pt64, a.hot_in_lds, block, lds_launch) * ctx->ncu;
+        if (a.nframes > cap) grid = (int)cap;
+    }
+    const bool claimed = grid < a.nframes;
+    const bool ordered = claimed && ctx->dispatch_order;
     const size_t nf4 = lpdec::lp_align(4 * (size_t)a.nframes);
-    const size_t extra = ordered ? 2 * nf4 + lpdec::lp_align(4 * ((size_t)code->m + 1)) : 0;
-    hipError_t e = ws_ensure(ws, per * (size_t)a.nframes + extra);
+    const size_t ord_bytes = ordered ? 2 * nf4 + lpdec::lp_align(4 * ((size_t)code->m + 1)) : 0;
+    const size_t extra = ord_bytes + (claimed ? 256 : 0);
+    hipError_t e = ws_ensure(ws, per * (size_t)grid + extra);
     if (e != hipSuccess) return hipfail(ctx, e, "workspace allocation");
     a.cold_ws = ws.ptr;
-    a.hot_ws = ws.ptr + a.cold_stride * (size_t)a.nframes;
+    a.hot_ws = ws.ptr + a.cold_stride * (size_t)grid;
     a.order = nullptr;
+    a.next = nullptr;
+    char *base = ws.ptr + per * (size_t)grid;
     if (ordered) {
-        char *base = ws.ptr + per * (size_t)a.nframes;
         int32_t *order = (int32_t *)base, *w = (int32_t *)(base + nf4), *hist = (int32_t *)(base + 2 * nf4);
         e = lpdec::launch_order(a, order, w, hist, stream);
         if (e != hipSuccess) return hipfail(ctx, e, "order launch");
         a.order = order;
     }
-    int block = ctx->block > 0 ? ctx->block : auto_block(code);
-    e = lpdec::launch_main(a, pt64, block, a.hot_in_lds ? lds_need : lds_dense, stream);
+    if (claimed) {
+        a.next = (int32_t *)(base + ord_bytes);
+        e = lpdec::launch_clear(a.next, 1, stream);
+        if (e != hipSuccess) return hipfail(ctx, e, "counter clear");
+    }
+    e = lpdec::launch_main(a, pt64, block, lds_launch, stream, grid);
     if (e != hipSuccess) return hipfail(ctx, e, "kernel launch");
     return LPDEC_OK;
 }
@@ -253,6 +269,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_PRECOND: if (!(ipos(0) && v <= 4)) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_STREAMS: if (!ipos(1) || v > 32) break; ctx->server_streams = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_MODE: if (v != 0 && v != 1) break; ctx->server_mode = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_DISPATCH_ORDER: if (v != 0 && v != 1) break; ctx->dispatch_order = (int)v; return LPDEC_OK;
     case LPDEC_OPT_XI_TOL: if (!(v > 0 && v < 1)) break; o.xi_tol = v; return LPDEC_OK;
     case LPDEC_OPT_IPM_STALL: if (!(v >= 0 && v < 1)) break; o.eps_stall = v; return LPDEC_OK;
     case LPDEC_OPT_DIRECT_FALLBACK: if (v != 0 && v != 1) break; o.direct = (int)v; return LPDEC_OK;
@@ -287,6 +304,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_PRECOND: *v = o.precond; break;
     case LPDEC_OPT_SERVER_STREAMS: *v = ctx->server_streams; break;
     case LPDEC_OPT_SERVER_MODE: *v = ctx->server_mode; break;
+    case LPDEC_OPT_DISPATCH_ORDER: *v = ctx->dispatch_order; break;
     case LPDEC_OPT_XI_TOL: *v = o.xi_tol; break;
     case LPDEC_OPT_IPM_STALL: *v = o.eps_stall; break;
     case LPDEC_OPT_DIRECT_FALLBACK: *v = o.direct; break;

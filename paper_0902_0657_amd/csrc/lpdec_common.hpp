@@ -188,7 +188,9 @@ struct Args {
     double *obj;               // [nframes]
     int32_t *done;             // [nframes], nullable: set to 1 once the frame's outputs are
                                // visible to the host (outputs in host-mapped memory)
-    const int32_t *order;      // MODE_DECODE, nullable: workgroup b decodes frame order[b]
+    const int32_t *order;      // MODE_DECODE with next, nullable: the k-th frame taken is order[k]
+    int32_t *next;             // MODE_DECODE, nullable: a grid smaller than the batch, whose
+                               // workgroups take frames in turn from *next (zero at launch)
     // MODE_SERVE: frames are ring slots; ticket t (claimed once, in order, from claim[0] while
     // t < *published) is slot t mod ring. claim[1] counts the workgroups holding or claiming a
     // ticket; claim[2] closes the launch: set by a workgroup that has polled idle_polls times

@@ -9,6 +9,26 @@
 
 namespace lpdec {
 
+// A batch larger than the device holds at once: the grid is one resident set of workgroups,
+// and each takes the next frame from a counter as it finishes one. Left to the hardware, the
+// workgroups of a larger grid are dispatched strictly in index order, workgroup b to XCD
+// b mod 8, so a compute unit that frees up waits until the next workgroup in line finds room on
+// its own XCD. Measured on the n=1024 batch, compute units idled a median 9.5 ms (at most
+// 185 ms) between frames.
+template <typename PT>
+LPD_INLINE void run_decode_claimed(Frame<PT> &F, const Args &a)
+{
+    for (;;) {
+        __syncthreads();   // the previous frame's last reads of the scratch area are done
+        if (F.tid == 0) F.sc->i[2] = __hip_atomic_fetch_add(a.next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int k = F.sc->i[2];
+        __syncthreads();
+        if (k >= a.nframes) return;
+        F.decode(a, a.order ? a.order[k] : k);
+    }
+}
+
 template <typename PT>
 LPD_INLINE void run_ipm(Frame<PT> &F, const Args &a, int f)
 {
@@ -194,7 +214,10 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
     F.bind(a, hot, cold, &sc);
     // tiles of the dense fallback follow the hot arena in dynamic LDS
     F.ldsd = a.plan.dense_on ? (double *)(lds_dyn + (HOT_LDS ? lp_align(a.plan.hot_bytes) : 0)) : nullptr;
-    if constexpr (MODE == MODE_DECODE) F.decode(a, a.order ? a.order[f] : f);
+    if constexpr (MODE == MODE_DECODE) {
+        if (a.next) run_decode_claimed(F, a);
+        else F.decode(a, f);
+    }
     else if constexpr (MODE == MODE_IPM) run_ipm(F, a, f);
     else if constexpr (MODE == MODE_SOLVE) run_solve(F, a, f);
     else if constexpr (MODE == MODE_MATVEC) run_matvec(F, a, f);
@@ -310,7 +333,7 @@ hipError_t launch_order(const Args &a, int32_t *order, int32_t *w, int32_t *hist
 }
 
 template <typename PT, bool HOT_LDS, int MODE>
-static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream_t stream)
+static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream_t stream, int grid)
 {
     // the per-thread error state is shared with every other HIP user of the thread: drop an
     // unread error left by an earlier call so that only this launch is checked below
@@ -322,31 +345,52 @@ static hipError_t launch_t(const Args &a, int block, size_t lds_bytes, hipStream
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(a.nframes), dim3(block), lds_bytes, stream, a);
+    hipLaunchKernelGGL((lpdec_main<PT, HOT_LDS, MODE>), dim3(grid), dim3(block), lds_bytes, stream, a);
     return hipGetLastError();
 }
 
 template <typename PT, bool HOT_LDS>
-static hipError_t launch_m(const Args &a, int block, size_t lds_bytes, hipStream_t stream)
+static hipError_t launch_m(const Args &a, int block, size_t lds_bytes, hipStream_t stream, int grid)
 {
     switch (a.mode) {
-    case MODE_DECODE: return launch_t<PT, HOT_LDS, MODE_DECODE>(a, block, lds_bytes, stream);
-    case MODE_IPM: return launch_t<PT, HOT_LDS, MODE_IPM>(a, block, lds_bytes, stream);
-    case MODE_SOLVE: return launch_t<PT, HOT_LDS, MODE_SOLVE>(a, block, lds_bytes, stream);
-    case MODE_MATVEC: return launch_t<PT, HOT_LDS, MODE_MATVEC>(a, block, lds_bytes, stream);
-    case MODE_MTS: return launch_t<PT, HOT_LDS, MODE_MTS>(a, block, lds_bytes, stream);
-    case MODE_CUTS: return launch_t<PT, HOT_LDS, MODE_CUTS>(a, block, lds_bytes, stream);
-    case MODE_SERVE: return launch_t<PT, HOT_LDS, MODE_SERVE>(a, block, lds_bytes, stream);
+    case MODE_DECODE: return launch_t<PT, HOT_LDS, MODE_DECODE>(a, block, lds_bytes, stream, grid);
+    case MODE_IPM: return launch_t<PT, HOT_LDS, MODE_IPM>(a, block, lds_bytes, stream, grid);
+    case MODE_SOLVE: return launch_t<PT, HOT_LDS, MODE_SOLVE>(a, block, lds_bytes, stream, grid);
+    case MODE_MATVEC: return launch_t<PT, HOT_LDS, MODE_MATVEC>(a, block, lds_bytes, stream, grid);
+    case MODE_MTS: return launch_t<PT, HOT_LDS, MODE_MTS>(a, block, lds_bytes, stream, grid);
+    case MODE_CUTS: return launch_t<PT, HOT_LDS, MODE_CUTS>(a, block, lds_bytes, stream, grid);
+    case MODE_SERVE: return launch_t<PT, HOT_LDS, MODE_SERVE>(a, block, lds_bytes, stream, grid);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream)
+hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream, int grid)
 {
-    if (pt64) return a.hot_in_lds ? launch_m<double, true>(a, block, lds_bytes, stream)
-                                  : launch_m<double, false>(a, block, lds_bytes, stream);
-    return a.hot_in_lds ? launch_m<float, true>(a, block, lds_bytes, stream)
-                        : launch_m<float, false>(a, block, lds_bytes, stream);
+    if (pt64) return a.hot_in_lds ? launch_m<double, true>(a, block, lds_bytes, stream, grid)
+                                  : launch_m<double, false>(a, block, lds_bytes, stream, grid);
+    return a.hot_in_lds ? launch_m<float, true>(a, block, lds_bytes, stream, grid)
+                        : launch_m<float, false>(a, block, lds_bytes, stream, grid);
+}
+
+int decode_per_cu(int pt64, int hot_in_lds, int block, size_t lds_bytes)
+{
+    const void *fn = pt64 ? (hot_in_lds ? (const void *)lpdec_main<double, true, MODE_DECODE>
+                                        : (const void *)lpdec_main<double, false, MODE_DECODE>)
+                          : (hot_in_lds ? (const void *)lpdec_main<float, true, MODE_DECODE>
+                                        : (const void *)lpdec_main<float, false, MODE_DECODE>);
+    if (lds_bytes > 0)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds_bytes) != hipSuccess || nb < 1) nb = 1;
+    (void)hipGetLastError();
+    return nb;
+}
+
+hipError_t launch_clear(int32_t *p, int n, hipStream_t stream)
+{
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(order_clear, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 }  // namespace lpdec

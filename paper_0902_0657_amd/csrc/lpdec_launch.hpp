@@ -8,7 +8,11 @@ namespace lpdec {
 
 // Launches one workgroup per frame. pt64: PCG in FP64 (1) or FP32 (0). lds_bytes: dynamic
 // LDS for the hot arena when a.hot_in_lds.
-hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream, int grid);
+// Workgroups of the decode kernel (MODE_DECODE) that one compute unit holds at once.
+int decode_per_cu(int pt64, int hot_in_lds, int block, size_t lds_bytes);
+// Zeroes n ints on `stream` with a kernel (no memset node when the stream is captured).
+hipError_t launch_clear(int32_t *p, int n, hipStream_t stream);
 // Static LDS used by the kernel besides the hot arena.
 size_t static_lds_bytes();
 // Dispatch order of a decode batch (a.nframes frames of a.gamma): order[0..nframes) lists the

@@ -284,14 +284,18 @@ def test_autotune_block(ctx, orc, tmp_path):
         autotune._CACHE.clear()
 
 
-def test_dispatch_order_does_not_change_results(ctx):
-    """A batch larger than the device holds at once is decoded in the order of descending
-    syndrome weight: each output, the LP point u and the iteration counts must still belong to
-    their own frame. The same frames decoded in batches of 100 (no reordering) give identical
-    results."""
+@pytest.mark.parametrize("order", [0, 1])
+def test_claimed_frames_and_dispatch_order_do_not_change_results(order):
+    """A batch larger than the device holds at once (300 frames at 256 threads, one workgroup
+    per compute unit) runs as one resident set of workgroups that take the frames in turn, in
+    index order or, with DISPATCH_ORDER 1, by descending syndrome weight: each output, the LP
+    point u and the iteration counts must still belong to their own frame. The same frames
+    decoded in batches of 100 (one workgroup per frame) give identical results."""
     import torch
+    from paper_0902_0657_amd import Code
+    ctx = make_ctx(DISPATCH_ORDER=order, BLOCK=256)
     code = regular_code(96)
-    C = _code(ctx, code)
+    C = Code.from_synth(ctx, code)
     G = np.concatenate([batch_awgn(code.n, 0.5, s, 150, stream=404, snr_index=i)
                         for i, s in enumerate((1.5, 3.0))])
     big = ctx.decode_batch(C, cuda(G, torch.float64), want_u=True)
@@ -304,3 +308,4 @@ def test_dispatch_order_does_not_change_results(ctx):
     sa = host(big["stats"])
     sb = np.concatenate([host(p["stats"]) for p in parts])
     assert np.array_equal(sa[:, :10], sb[:, :10])   # the counts; the clock ticks vary
+    ctx.close()
