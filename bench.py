@@ -361,7 +361,7 @@ def main():
                     help="print the preconditioner comparison of Sec. VI-B (n=2000 code) instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: frames are independent LPs and the "
+        print(json.dumps({"error": "the benchmark measures one GPU: frames are independent LPs and the "
                                    "multi-GPU form is a per-frame shard with no exchange; "
                                    "run with --gpus 1"}))
         sys.exit(2)
