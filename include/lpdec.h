@@ -53,6 +53,8 @@ typedef int32_t lpdec_status;
 #define LPDEC_FLAG_NONFINITE (-2)   /* non-finite iterate (e.g. NaN/Inf in gamma) */
 #define LPDEC_FLAG_MALP_CAP (-3)    /* MALP iteration cap reached with cuts still violated */
 #define LPDEC_FLAG_INCONSISTENT (-4)/* integral output that violates a check */
+#define LPDEC_FLAG_COST_DECREASE (-5)/* an LP's cost fell below the previous LP's beyond TAU_COST
+                                        (impossible in exact arithmetic, Theorem 2b) */
 
 typedef struct lpdec_ctx lpdec_ctx;
 typedef struct lpdec_code lpdec_code;
@@ -152,6 +154,10 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  and is launched again on the next one. An engine holds its
  *                  workspace until the server is destroyed or its budget is needed by another
  *                  code's engine while it has no work. Results are bit-identical to mode 0
+ *   TAU_COST       the costs gamma^T u of successive LP solutions increase strictly
+ *                  (Theorem 2b); a decrease by more than TAU_COST (1 + c^T x) ends the decode
+ *                  with LPDEC_FLAG_COST_DECREASE (1e-8). Every LP solution is put back on
+ *                  the box [0, 1]^n (Theorem 2a) before the cut search
  *   DISPATCH_ORDER 1 (default) = a decode batch larger than the device holds at once takes
  *                  its frames hardest-first (see lpdec_decode_batch); 0 = in index order.
  *                  Results do not depend on it
@@ -163,7 +169,7 @@ enum {
     LPDEC_OPT_MALP_MAX, LPDEC_OPT_BLOCK, LPDEC_OPT_PRECOND, LPDEC_OPT_XI_TOL,
     LPDEC_OPT_IPM_STALL, LPDEC_OPT_DIRECT_FALLBACK, LPDEC_OPT_MTS_REUSE, LPDEC_OPT_WARM_START,
     LPDEC_OPT_SERVER_STREAMS, LPDEC_OPT_IPM_WARM, LPDEC_OPT_SERVER_MODE,
-    LPDEC_OPT_DISPATCH_ORDER, LPDEC_OPT__COUNT
+    LPDEC_OPT_DISPATCH_ORDER, LPDEC_OPT_TAU_COST, LPDEC_OPT__COUNT
 };
 lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double value);
 lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, double *value);

@@ -51,6 +51,8 @@ typedef struct {
     double eta;      /* fraction-to-boundary factor */
     double eps;      /* IPM termination tolerance */
     double eps_stall;/* below it, an iteration that makes no progress ends the IPM */
+    double tau_cost; /* a cost decrease beyond tau_cost (1 + |c^T x|) between LPs is a failure */
+    int box_clamp;   /* 1: u^k is put back on [0, 1]^n before Algorithm 2 (tests set 0) */
 } orc_opts;
 
 typedef struct {
@@ -58,7 +60,7 @@ typedef struct {
     int ipm_iters;       /* IPM iterations summed over LPs */
     int p_max;           /* largest number of cuts in one LP */
     int p_final;         /* cuts in the last LP */
-    int status;          /* 0 ok, -1 IPM cap, -3 MALP cap, -2 non-finite */
+    int status;          /* 0 ok, -1 IPM cap, -3 MALP cap, -2 non-finite, -5 cost decrease */
 } orc_stats;
 
 /* ------------------------------------------------------------------------------------ */
@@ -346,7 +348,12 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
     double *y = malloc(sizeof(double) * (m + 1));
     orc_stats s = {0, 0, 0, 0, 0};
     /* initial LP: box constraints only; its solution is the bit-wise hard decision */
-    for (int i = 0; i < n; ++i) u[i] = gamma[i] >= 0.0 ? 0.0 : 1.0;
+    double gneg = 0.0;                                /* gamma^T u at the hard decision */
+    for (int i = 0; i < n; ++i) {
+        u[i] = gamma[i] >= 0.0 ? 0.0 : 1.0;
+        if (gamma[i] < 0.0) gneg += gamma[i];
+    }
+    double cost_prev = gneg;                          /* gamma^T u^(k-1) */
     int k;
     for (k = 0; k < o->malp_max; ++k) {
         int added = 0;
@@ -373,7 +380,18 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
         s.ipm_iters += its;
         if (lp.p > s.p_max) s.p_max = lp.p;
         s.p_final = lp.p;
-        for (int i = 0; i < n; ++i) u[i] = gamma[i] >= 0.0 ? x[i] : 1.0 - x[i];
+        /* u^k from the LP solution (Sec. IV-B variable flip). Every u^k satisfies the box
+           constraints (Theorem 2a), which are not all in the LP: a coordinate the IPM leaves
+           slightly outside [0, 1] (one whose cost |gamma_i| is too small for the gap test to
+           pin it) is put back on the box before Algorithm 2 looks at it, so that rounding
+           cannot produce a violated cut (Theorem 1 assumes u in [0, 1]^n). */
+        double cost = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double ui = gamma[i] >= 0.0 ? x[i] : 1.0 - x[i];
+            if (o->box_clamp) ui = ui < 0.0 ? 0.0 : (ui > 1.0 ? 1.0 : ui);
+            u[i] = ui;
+            cost += gamma[i] * ui;
+        }
         for (int r = 0; r < lp.p; ++r) {
             double sl = x[n + r], zs = z[n + r];
             active[lp.rowchk[r]] = !(sl > (o->tau_act > zs ? o->tau_act : zs));
@@ -388,6 +406,12 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
         }
         lp_free(&lp);
         if (rc != 0) { s.status = rc; break; }
+        /* Theorem 2b: the costs of successive LP solutions increase strictly. A decrease
+           beyond the IPM's accuracy (relative to 1 + c^T x, the scale of its gap test; c^T x
+           = gamma^T u - gneg) means a cut was replaced or dropped while it still bound the
+           optimum: the decode stops with a failure flag instead of cycling. */
+        if (cost < cost_prev - o->tau_cost * (1.0 + fabs(cost_prev - gneg))) { s.status = -5; break; }
+        cost_prev = cost;
     }
     if (k == o->malp_max && s.status == 0) s.status = -3;
     /* output: integrality, hard decision of the LP solution, syndrome, objective */

@@ -9,11 +9,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblpdec.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT = -1, -2, -3, -4
+FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT, FLAG_COST_DECREASE = -1, -2, -3, -4, -5
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",
-    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL", "DIRECT_FALLBACK", "MTS_REUSE", "WARM_START", "SERVER_STREAMS", "IPM_WARM", "SERVER_MODE", "DISPATCH_ORDER"])}
+    "PCG_TOL", "PCG_MAXIT", "REF_TOL", "REF_MAX", "IPM_MAX", "MALP_MAX", "BLOCK", "PRECOND", "XI_TOL", "IPM_STALL", "DIRECT_FALLBACK", "MTS_REUSE", "WARM_START", "SERVER_STREAMS", "IPM_WARM", "SERVER_MODE", "DISPATCH_ORDER", "TAU_COST"])}
 
 
 class Stats(C.Structure):

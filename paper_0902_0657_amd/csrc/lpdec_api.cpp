@@ -114,6 +114,7 @@ void default_opts(lpdec::Opts &o)
     o.tau_int = 1e-4;
     o.eps = 1e-8;
     o.eps_stall = 1e-7;
+    o.tau_cost = 1e-8;
     o.sigma = 0.1;
     o.eta = 0.9995;
     o.pcg_tol = 1e-6;
@@ -276,6 +277,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
     case LPDEC_OPT_MTS_REUSE: if (!ipos(1) || v > 1000) break; o.mts_reuse = (int)v; return LPDEC_OK;
     case LPDEC_OPT_WARM_START: if (v != 0 && v != 1) break; o.warm = (int)v; return LPDEC_OK;
     case LPDEC_OPT_IPM_WARM: if (!(v >= 0 && v <= 10)) break; o.ipm_warm = v; return LPDEC_OK;
+    case LPDEC_OPT_TAU_COST: if (!(v >= 0 && v <= 1)) break; o.tau_cost = v; return LPDEC_OK;
     default: return fail(ctx, LPDEC_EINVAL, "unknown option key %d", key);
     }
     return fail(ctx, LPDEC_EINVAL, "bad value %g for option %d", v, key);
@@ -311,6 +313,7 @@ extern "C" lpdec_status lpdec_get_option(const lpdec_ctx *ctx, int32_t key, doub
     case LPDEC_OPT_MTS_REUSE: *v = o.mts_reuse; break;
     case LPDEC_OPT_WARM_START: *v = o.warm; break;
     case LPDEC_OPT_IPM_WARM: *v = o.ipm_warm; break;
+    case LPDEC_OPT_TAU_COST: *v = o.tau_cost; break;
     default: return LPDEC_EINVAL;
     }
     return LPDEC_OK;

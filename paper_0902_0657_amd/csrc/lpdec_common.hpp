@@ -21,6 +21,7 @@ struct Opts {
     double ipm_warm; // > 0: an LP after the first starts from the previous LP's point, shifted by this
     double tau_viol, tau_act, tau_int;
     double eps, eps_stall, sigma, eta;
+    double tau_cost; // a cost decrease between successive LPs beyond tau_cost (1 + c^T x) fails the decode
     double pcg_tol, ref_tol, xi_tol;
 };
 

@@ -1983,10 +1983,15 @@ struct Frame {
         ticks_pcg = 0;
         const long long t_start = wall_clock64();
         load_gamma(a, f);
-        for (int i = tid; i < n; i += nt) u[i] = g[i] >= 0.0 ? 0.0 : 1.0;   // hard decision
+        double gneg = 0.0;   // gamma^T u at the hard decision
+        for (int i = tid; i < n; i += nt) {
+            u[i] = g[i] >= 0.0 ? 0.0 : 1.0;   // hard decision
+            if (g[i] < 0.0) gneg += g[i];
+        }
         for (int j = tid; j < m; j += nt) { vmask[j] = 0u; active[j] = 0; vprev[j] = 0u; }
         have_prev = false;
-        __syncthreads();
+        gneg = block_sum1(gneg, sc);
+        double cost_prev = gneg;   // gamma^T u of the previous LP's solution
         int status = 0, k;
         for (k = 0; k < o.malp_max; ++k) {
             int added = 0;
@@ -2008,14 +2013,30 @@ struct Frame {
             st.malp_iters++;
             st.ipm_iters += its;
             st.p_max = max(st.p_max, p);
-            for (int i = tid; i < n; i += nt) u[i] = sg[i] > 0 ? x[i] : 1.0 - x[i];
+            // u^k from the LP solution, put back on the box [0, 1]^n that every u^k satisfies
+            // (Theorem 2a): a coordinate of tiny cost that the gap test leaves slightly
+            // outside would otherwise let Algorithm 2 report a violated cut from rounding
+            double cost = 0.0;
+            for (int i = tid; i < n; i += nt) {
+                const double ui = fmin(1.0, fmax(0.0, sg[i] > 0 ? x[i] : 1.0 - x[i]));
+                u[i] = ui;
+                cost += g[i] * ui;
+            }
             for (int j = tid; j < m; j += nt) {
                 if (!cut(j)) { active[j] = 0; continue; }
                 const double sl = x[n + j], zs = z[n + j];
                 active[j] = !(sl > (o.tau_act > zs ? o.tau_act : zs));
             }
-            __syncthreads();
+            cost = block_sum1(cost, sc);
             if (status < 0) break;
+            // Theorem 2b: successive LP costs increase strictly. A decrease beyond the IPM's
+            // accuracy (relative to 1 + c^T x, c^T x = gamma^T u - gneg) means a cut that still
+            // bound the optimum was replaced or dropped; the decode ends with a failure flag
+            if (cost < cost_prev - o.tau_cost * (1.0 + fabs(cost_prev - gneg))) {
+                status = LPDEC_FLAG_COST_DECREASE;
+                break;
+            }
+            cost_prev = cost;
         }
         if (k == o.malp_max && status == 0) status = LPDEC_FLAG_MALP_CAP;
         // output: integrality, decisions, syndrome, objective gamma^T u

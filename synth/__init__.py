@@ -6,4 +6,4 @@ experiments draw at random (random 4-cycle-free (3,6)-regular codes over AWGN, S
 and Sec. VI-B).
 """
 from .codes import Code, regular_code, irregular_code, code_for_config  # noqa: F401
-from .channel import awgn_llr, bsc_llr, frame_seed, splitmix64  # noqa: F401
+from .channel import awgn_llr, bsc_llr, frame_seed, splitmix64, uniform_snr_awgn  # noqa: F401

@@ -59,3 +59,12 @@ def batch_awgn(n: int, rate: float, ebn0_db: float, nframes: int, stream: int,
 def batch_bsc(n: int, p: float, nframes: int, stream: int, first_frame: int = 0) -> np.ndarray:
     return np.stack([bsc_llr(n, p, frame_seed(stream, 0, f))
                      for f in range(first_frame, first_frame + nframes)])
+
+
+def uniform_snr_awgn(n: int, lo: float, hi: float, stream: int, frame: int,
+                     rate: float = 0.5) -> tuple[float, np.ndarray]:
+    """One frame at an Eb/N0 drawn uniformly from [lo, hi] dB: returns (Eb/N0, gamma).
+    The Eb/N0 comes from its own seed (SNR index 1), the noise from SNR index 0."""
+    u = np.random.Generator(np.random.PCG64(frame_seed(stream, 1, frame))).random()
+    e = lo + (hi - lo) * float(u)
+    return e, awgn_llr(n, e, rate, frame_seed(stream, 0, frame))

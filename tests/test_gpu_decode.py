@@ -27,34 +27,19 @@ def _code(ctx, code):
     return Code.from_synth(ctx, code)
 
 
-# A fractional LP optimum can sit on a nearly flat face of the polytope: the objective moves by
-# less than the IPM's tolerance while coordinates near 1/2 move by ~1e-3, so their rounding is
-# not determined by the LP (HiGHS' simplex vertex and the oracle's interior point differ there
-# too). Where allowed, a fractional frame may differ from the oracle only in decisions whose
-# u is within FLAT of 1/2 on both sides; flag and objective must still agree.
-FLAT = 1e-2
-
-
-def _compare(orc, code, G, out, oracle_frames=None, opts=None, allow_flat=False):
+def _compare(orc, code, G, out, oracle_frames=None, opts=None):
+    """Every listed frame equal to the oracle: flag and decoded word bit-exact, objective within
+    1e-6 relative to the IPM's gap scale."""
     xh, fl, ob = host(out["xhat"]), host(out["flag"]), host(out["obj"])
-    ug = host(out["u"]) if "u" in out else None
     frames = range(G.shape[0]) if oracle_frames is None else oracle_frames
-    bad, flat = [], []
+    bad = []
     for f in frames:
         r = orc.decode(code, G[f], opts)
         if not (fl[f] == r.flag and obj_close(ob[f], r.objective, G[f])):
             bad.append((f, int(fl[f]), r.flag, float(ob[f]), r.objective))
-            continue
-        if np.array_equal(xh[f], r.xhat):
-            continue
-        d = np.nonzero(xh[f] != r.xhat)[0]
-        if (allow_flat and r.flag == 0 and ug is not None and np.all(np.abs(r.u[d] - 0.5) <= FLAT)
-                and np.all(np.abs(ug[f][d] - 0.5) <= FLAT)):
-            flat.append((f, d.tolist()))
-        else:
-            bad.append((f, "decisions", d[:8].tolist()))
+        elif not np.array_equal(xh[f], r.xhat):
+            bad.append((f, "decisions", np.nonzero(xh[f] != r.xhat)[0][:8].tolist()))
     assert not bad, bad[:5]
-    return flat
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -196,41 +181,60 @@ def test_preconditioner_reuse_and_warm_start(ctx, orc, opt, val):
         assert sr["mts_rounds"].sum() < s1["mts_rounds"].sum()
 
 
-def _n1024_batch():
-    """The benchmark's workload: (3,6) n=1024, 171/171/170 frames at Eb/N0 1.5/2.0/2.5 dB,
-    FP32 LLRs, one launch of 512 frames."""
-    code = regular_code(1024)
-    snrs, split = [1.5, 2.0, 2.5], [171, 171, 170]
-    G = np.concatenate([batch_awgn(code.n, 0.5, s, k, stream=2024, snr_index=i)
-                        for i, (s, k) in enumerate(zip(snrs, split))]).astype(np.float32)
-    return code, G
-
-
-def test_config2_n1024_full_batch(ctx, orc):
-    """The benchmark's launch (512 frames, FP32 LLRs, default precision). Every frame: p <= m
-    (Corollary 3), no numerical failure, u inside the fundamental polytope up to the violation
-    threshold at which MALP stops adding cuts, a flag-1 frame's
-    decisions satisfy every check and equal its LP solution. A sample of frames from every
-    Eb/N0 group, fractional ones included, is checked against the oracle."""
+def test_malp_cycle_frame(ctx, orc):
+    """The n=256 frame whose LLR gamma_164 is about -3e-6: without the box clamp of Theorem 2a
+    the cut sets alternate with period 2 up to the MALP cap. Both sides must reach the LP
+    optimum with flag 1, in both MALP modes."""
     import torch
-    from tests import refs
-    code, G = _n1024_batch()
+    from synth.channel import awgn_llr, frame_seed
+    code = regular_code(256)
     C = _code(ctx, code)
-    out = ctx.decode_batch(C, cuda(G, torch.float32), want_u=True)
-    torch.cuda.synchronize()
-    st, fl, xh, u = host(out["stats"]), host(out["flag"]), host(out["xhat"]), host(out["u"])
-    assert np.all(st[:, 3] <= code.m) and np.all(fl >= 0)
-    H = code.dense()
-    for f in range(G.shape[0]):
-        # MALP stops once no inequality is violated by more than TAU_VIOL (1e-4)
-        assert refs.max_parity_violation(code, u[f]) < 1e-4 + 1e-6, f
-        if fl[f] == 1:
-            assert not ((H @ xh[f]) % 2).any() and np.array_equal(xh[f], (u[f] > 0.5).astype(np.uint8)), f
-    # frames 8 and 53 end at the double-precision floor of the IPM; 62 and 153 are fractional
-    # frames with a degenerate last LP
-    sample = [0, 1, 2, 8, 53, 62, 153, 171, 172, 173, 342, 343, 344]
-    flat = _compare(orc, code, G.astype(np.float64), out, oracle_frames=sample, allow_flat=True)
-    print("decisions on a flat optimal face:", flat)
+    G = awgn_llr(code.n, 1.6537604712821115, 0.5, frame_seed(91, 0, 145))[None, :]
+    for mode in (0, 1):
+        ctx.set_option("MALP_MODE", mode)
+        try:
+            out = ctx.decode_batch(C, cuda(G, torch.float64))
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option("MALP_MODE", 0)
+        assert host(out["flag"])[0] == 1
+        _compare(orc, code, G, out, opts=orc.OracleOpts(malp_mode=mode))
+
+
+def _sweep_oracle(args):
+    import oracle as O
+    n, mode, f = args
+    from synth.channel import uniform_snr_awgn
+    _, gamma = uniform_snr_awgn(n, 1.5, 3.0, 92, f)
+    r = O.decode(regular_code(n), gamma, O.OracleOpts(malp_mode=mode))
+    return r.xhat, r.flag, r.objective
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_uniform_snr_sweep_n256(ctx, orc, mode):
+    """2000 frames of the n=256 code, Eb/N0 uniform in [1.5, 3] dB, in one launch (a resident
+    set of workgroups taking frames in turn): no negative flag, and every frame equal to the
+    oracle, strictly."""
+    import multiprocessing as mp
+    import torch
+    from synth.channel import uniform_snr_awgn
+    n, F = 256, 2000
+    code = regular_code(n)
+    C = _code(ctx, code)
+    G = np.stack([uniform_snr_awgn(n, 1.5, 3.0, 92, f)[1] for f in range(F)])
+    ctx.set_option("MALP_MODE", mode)
+    try:
+        out = ctx.decode_batch(C, cuda(G, torch.float64))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("MALP_MODE", 0)
+    xh, fl, ob = host(out["xhat"]), host(out["flag"]), host(out["obj"])
+    assert np.all(fl >= 0), [(f, int(fl[f])) for f in np.nonzero(fl < 0)[0]][:10]
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        ref = pool.map(_sweep_oracle, [(n, mode, f) for f in range(F)], chunksize=16)
+    bad = [f for f in range(F) if not (fl[f] == ref[f][1] and np.array_equal(xh[f], ref[f][0])
+                                        and obj_close(ob[f], ref[f][2], G[f]))]
+    assert not bad, bad[:10]
 
 
 @pytest.mark.parametrize("block", [64, 256])

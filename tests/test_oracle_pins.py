@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from synth.channel import awgn_llr, batch_awgn, bsc_llr, frame_seed
+from synth.channel import awgn_llr, batch_awgn, bsc_llr, frame_seed, uniform_snr_awgn
 from synth.codes import from_dense, irregular_code, regular_code
 from tests import refs
 
@@ -117,7 +117,8 @@ def test_ipm_matches_highs_and_kkt(orc):
             u = np.where(gamma >= 0, x[:code.n], 1 - x[:code.n])
             fun, _ = refs.cutset_lp(code, gamma, masks)
             assert gamma @ u == pytest.approx(fun, rel=1e-6, abs=1e-6)
-            assert gamma @ u == pytest.approx(res.trace_obj[k], abs=1e-12)
+            # the decoder's u^k is the LP solution put back on the box (Theorem 2a)
+            assert gamma @ np.clip(u, 0.0, 1.0) == pytest.approx(res.trace_obj[k], abs=1e-12)
             checked += 1
     assert checked > 20
 
@@ -644,3 +645,58 @@ def test_triangulation_step_rejects_a_cycle(orc):
     code = from_dense(np.array([[1, 1, 0], [1, 1, 1]], dtype=np.int8))
     assert not triangulation_step(code, np.array([1, 1], np.uint8), np.array([0, 1], np.int32))
     assert triangulation_step(code, np.array([1, 1], np.uint8), np.array([0, 2], np.int32))
+
+
+# ---------------------------------------------------------------- Theorem 2a/2b in the MALP loop
+# A frame of the n=256 (3,6) code whose LLR gamma_164 is about -3e-6: the IPM leaves u_164 about
+# 1.6e-4 below 0 (its cost is too small for the gap test to pin it), which, without the box
+# clamp of Theorem 2a, makes Algorithm 2 report a violated cut at a left-hand side of 0.99984 and
+# MALP-A replace a cut that still binds; the cut sets then alternate with period 2.
+CYCLE_FRAME = dict(n=256, ebn0=1.6537604712821115, seed=frame_seed(91, 0, 145))
+
+
+def test_malp_cycle_frame_reaches_lp_optimum(orc):
+    code = regular_code(CYCLE_FRAME["n"])
+    gamma = awgn_llr(code.n, CYCLE_FRAME["ebn0"], 0.5, CYCLE_FRAME["seed"])
+    fun, ustar = refs.feldman_lp(code, gamma)
+    scale = 1.0 + abs(fun - gamma[gamma < 0].sum())
+    for mode in (0, 1):
+        res = orc.decode(code, gamma, orc.OracleOpts(malp_mode=mode), trace=True)
+        assert res.flag == 1, (mode, res.flag)
+        assert abs(res.objective - fun) <= 1e-6 * scale
+        assert np.array_equal(res.xhat, (ustar > 0.5).astype(np.uint8))
+        assert np.all(np.diff(res.trace_obj) > 0)          # Theorem 2b
+    # the planted mistake: no clamp. The cost check (Theorem 2b) ends the cycle at its first
+    # decrease; without the check the decode runs into the MALP cap
+    bad = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0), trace=True)
+    assert bad.flag == -5 and bad.malp_iters <= 4
+    assert bad.trace_obj[-1] < bad.trace_obj[-2]
+    worse = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0, tau_cost=1.0, malp_max=50))
+    assert worse.flag == -3
+
+
+def _sweep_frame(args):
+    import oracle as O
+    n, mode, f = args
+    code = regular_code(n)
+    e, gamma = uniform_snr_awgn(n, 1.5, 3.0, 92, f)
+    r = O.decode(code, gamma, O.OracleOpts(malp_mode=mode), trace=True)
+    gneg = gamma[gamma < 0].sum()
+    costs = np.concatenate([[gneg], r.trace_obj])
+    rel = np.diff(costs) / (1.0 + np.abs(costs[:-1] - gneg))
+    return f, e, r.flag, float(rel.min()) if rel.size else np.inf, float(r.u.min()), float(r.u.max())
+
+
+@pytest.mark.parametrize("n,mode,frames", [(256, 0, 2000), (256, 1, 2000), (1024, 0, 500)])
+def test_malp_sweep_no_failures(orc, n, mode, frames):
+    """No negative flag over a sweep of frames with Eb/N0 uniform in [1.5, 3] dB; every
+    decode's LP costs increase (Theorem 2b, within the IPM's relative accuracy) and its
+    output lies in the box (Theorem 2a)."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        res = pool.map(_sweep_frame, [(n, mode, f) for f in range(frames)], chunksize=8)
+    bad = [(f, e, fl) for f, e, fl, _, _, _ in res if fl < 0]
+    assert not bad, bad[:10]
+    assert min(r[3] for r in res) > -1e-8
+    assert min(r[4] for r in res) >= 0.0 and max(r[5] for r in res) <= 1.0
+    assert sum(r[2] == 0 for r in res) > frames // 50       # the sweep reaches fractional frames
