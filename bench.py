@@ -1,17 +1,24 @@
 """Benchmark: LP-decoded frames/s of the batched decoder on the (3,6)-regular n=1024 code.
 
 One step = one launch of the decoder over a batch of 512 frames (Eb/N0 1.5 / 2.0 / 2.5 dB,
-171/171/170 frames, FP32 LLRs, FP64 PCG with the dense FP64 fallback): every step of the hot path
-(cut search, cut update, interior-point iterations, triangular-set search, PCG) runs inside
-that launch. Inputs are resident in device memory before timing starts.
+171/171/170 frames, FP32 LLRs, FP32 PCG with FP64 refinement and FP64 interior-point
+iterations): every step of the hot path (cut search, cut update, interior-point iterations,
+triangular-set search, PCG) runs inside that launch. Inputs are resident in device memory
+before timing starts. Newton systems that PCG does not finish within its cap go to a dense
+FP64 Cholesky (the library's default); the method alone is the method_only leg.
 
-Prints one JSON line. Extra legs, each reported beside the main number:
-  plain_fp64   the same frames through lpdec_decode (FP64, one frame per launch, host
-               pointers), a bounded sample;
-  cpu_baseline the FP64 CPU oracle on the host cores, a time-bounded sample;
-  roofline     effective bandwidth of the decode kernel on its algorithmic bytes;
-  serving      Poisson arrivals of mixed-length frames through lpdec_server (persistent
-               engines, then the wave scheduler as serving_waves).
+Prints one JSON line. Beside the main number:
+  roofline        HBM bandwidth of the launch on the method's algorithmic bytes, with the
+                  PCG-only figure and the dense fallback's share
+  main            flags, parity of all 512 frames against the stored oracle results,
+                  per-frame decode times, decode statistics
+  method_only     the same batch without the dense fallback (FP64 PCG, cap 2000)
+  other_precision the same batch with the other PCG vector precision
+  serving         Poisson arrivals of mixed-length frames through lpdec_server (persistent
+                  engines, then the wave scheduler as serving_waves)
+  plain_fp64      frames through lpdec_decode (FP64, one frame per launch, host pointers)
+  cpu_baseline    the FP64 CPU oracle on the host cores, a time-bounded sample
+  config_c3/c4    (--configs c3,c4) one launch of the n=4096 / irregular n=8192 workloads
 """
 from __future__ import annotations
 
@@ -30,28 +37,30 @@ sys.path.insert(0, ROOT)
 # other work of this process
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 12:
     os.environ["GPU_MAX_HW_QUEUES"] = "12"
-
-N, SNRS, SPLIT = 1024, (1.5, 2.0, 2.5), (171, 171, 170)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6     # dense FP64 matrix-core peak of the chip
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+GOLDEN_FILES = {"c2": "c2_n1024.json", "c3": "c3_n4096.json", "c4": "c4_irr8192.json"}
+METRIC = "LP-decoded frames/s at n=1024 (3,6) + p50/p99 latency, vs plain FP64 GPU"
 
 
-def workload():
-    from synth.channel import batch_awgn
-    from synth.codes import regular_code
-    code = regular_code(N)
-    G = np.concatenate([batch_awgn(code.n, 0.5, s, k, stream=2024, snr_index=i)
-                        for i, (s, k) in enumerate(zip(SNRS, SPLIT))]).astype(np.float32)
-    return code, G
+def workload(name="c2"):
+    from synth.workloads import WORKLOADS
+    return WORKLOADS[name]()
 
 
-def algorithmic_bytes(st, n):
-    """Bytes the method must move per frame: per PCG iteration 27p + 4q
-    (q = n + p, FP32 vectors), per interior-point iteration 120q (FP64 vector passes)."""
-    pcg_rows = st["pcg_rows"].astype(np.float64)
-    pcg_its = st["pcg_iters"].astype(np.float64)
-    ipm_cols = st["ipm_cols"].astype(np.float64)
-    return float(np.sum(27 * pcg_rows + 4 * (pcg_its * n + pcg_rows) + 120 * ipm_cols))
+def pcg_bytes(st, n, elem):
+    """Bytes one PCG iteration must move, summed over the frames: (6e + 3) p + e q with e the
+    vector element size (27p + 4q for FP32 vectors: read h, d^2, the row map and the lists,
+    write l, update x, r and z; 16-bit indices), q = n + p."""
+    rows = st["pcg_rows"].astype(np.float64)
+    its = st["pcg_iters"].astype(np.float64)
+    return float(np.sum((6 * elem + 3) * rows + elem * (its * n + rows)))
+
+
+def ipm_bytes(st):
+    """FP64 vector passes of the interior-point iterations: 120 q bytes each."""
+    return float(np.sum(120 * st["ipm_cols"].astype(np.float64)))
 
 
 def dense_flops(st):
@@ -59,44 +68,146 @@ def dense_flops(st):
     return float(st["dense_cube"].astype(np.float64).sum() / 3.0)
 
 
+def rooflines(st, n, elem, kern_s, ncu, traffic=None, traffic_note=None):
+    """The launch's HBM roofline on the method's algorithmic bytes (PCG + IPM vector passes),
+    the PCG-only figure, and the dense fallback's flops beside them."""
+    pb, ib = pcg_bytes(st, n, elem), ipm_bytes(st)
+    alg = pb + ib
+    achieved = alg / kern_s / 1e9
+    pcg_s = float(st["ticks_pcg"].sum()) / 1e8          # device clock: 100 MHz
+    per_frame = pb / pcg_s / 1e9 if pcg_s > 0 else 0.0
+    its = int(st["pcg_iters"].sum())
+    flops = dense_flops(st)
+    return {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,
+        "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
+        "algorithmic_bytes_per_launch": alg, "pcg_bytes_per_launch": pb, "ipm_bytes_per_launch": ib,
+        "basis": f"per PCG iteration (6e+3)p + eq bytes, e = {elem} (vector element size), q = n + p; "
+                 "per IPM iteration 120q bytes; divided by the launch time (HIP events on its stream)",
+        "kernel_ms": kern_s * 1e3,
+        "pcg_only": {
+            "iterations": its, "us_per_iteration": pcg_s * 1e6 / max(1, its),
+            "frame_seconds_in_pcg": pcg_s,
+            "per_frame_GBps": per_frame,
+            "all_cus_GBps": per_frame * ncu, "all_cus_frac": per_frame * ncu / HBM_PEAK_GBS,
+            "note": "PCG bytes over the frames' device time inside PCG iterations; all_cus = that "
+                    "rate on every compute unit at once (one frame per compute unit)"},
+        "dense_fallback": {"bound": "mfma", "achieved": flops / kern_s / 1e12, "peak": FP64_PEAK_TFS,
+                           "unit": "TFLOP/s", "frac": flops / kern_s / 1e12 / FP64_PEAK_TFS,
+                           "flops_per_launch": flops,
+                           "basis": "Cholesky P^3/3 flops per dense-fallback solve (P = LP rows padded to 32), "
+                                    "FP64 matrix cores; work outside the method, reported for its share"},
+    }
+
+
+def decode_stats(st, nf):
+    tot = max(1, int(st["ticks_total"].sum()))
+    newton = int(st["ipm_iters"].sum())
+    return {"mean_malp_iters": float(st["malp_iters"].mean()), "max_malp_iters": int(st["malp_iters"].max()),
+            "lps_solved": int(st["malp_iters"].sum()),
+            "mean_ipm_iters": float(st["ipm_iters"].mean()),
+            "mean_pcg_iters": float(st["pcg_iters"].mean()),
+            "mean_pcg_per_newton": float(st["pcg_iters"].sum() / max(1, newton)),
+            "max_p": int(st["p_max"].max()), "mean_p_max": float(st["p_max"].mean()),
+            "max_levels": int(st["max_levels"].max()),
+            "pcg_us_per_iteration": float(st["ticks_pcg"].sum() / 100.0 / max(1, st["pcg_iters"].sum())),
+            "mts_us_per_ipm_iteration": float(st["ticks_mts"].sum() / 100.0 / max(1, newton)),
+            "ref_rounds": int(st["ref_rounds"].sum()), "escalations": int(st["escalations"].sum()),
+            "newton_solves": newton, "dense_fallback_solves": int(st["direct_solves"].sum()),
+            "newton_solved_by_pcg": 1.0 - float(st["direct_solves"].sum() / max(1, newton)),
+            "device_time_share": {"pcg": float(st["ticks_pcg"].sum()) / tot,
+                                  "dense_fallback": float(st["ticks_dense"].sum()) / tot,
+                                  "mts": float(st["ticks_mts"].sum()) / tot}}
+
+
+def golden_parity(name, code, G, flags, xhat, objs):
+    """Frames of a launch against the stored oracle results (tests/golden, written by an
+    oracle-only script): decoded word and flag bit-exact, objective within 1e-6 relative to
+    1 + c^T x."""
+    path = os.path.join(GOLDEN, GOLDEN_FILES[name])
+    if not os.path.exists(path):
+        return None
+    gold = json.load(open(path))["frames"]
+    bad = []
+    for k, rec in gold.items():
+        f = int(k)
+        want = np.unpackbits(np.frombuffer(bytes.fromhex(rec["xhat_hex"]), np.uint8))[:code.n]
+        g = G[f].astype(np.float64)
+        scale = 1.0 + abs(rec["objective"] - float(g[g < 0].sum()))
+        if not (flags[f] == rec["flag"] and np.array_equal(xhat[f], want)
+                and abs(objs[f] - rec["objective"]) <= 1e-6 * scale):
+            bad.append(f)
+    return {"frames": len(gold), "mismatches": len(bad), "mismatched_frames": bad[:20],
+            "source": f"tests/golden/{GOLDEN_FILES[name]} (oracle results)"}
+
+
 def _oracle_worker(args):
-    code_spec, gamma = args
+    name, f = args
     import oracle
-    from synth.codes import regular_code
-    code = regular_code(code_spec)
+    code, G = workload(name)
     t = time.perf_counter()
-    r = oracle.decode(code, gamma)
+    r = oracle.decode(code, G[f].astype(np.float64))
     return time.perf_counter() - t, r.xhat, r.flag, r.objective
 
 
-def cpu_baseline(G, budget_s=12.0):
-    from concurrent.futures import ProcessPoolExecutor, FIRST_COMPLETED, wait
-    import oracle
-    oracle.build(force=False)
+def host_cores():
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
-    workers = max(1, min(avail, 16))
+    lscpu = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu", "-p=CPU"], capture_output=True, text=True, timeout=10).stdout
+        lscpu = sum(1 for line in out.splitlines() if line and not line.startswith("#"))
+    except Exception:
+        pass
+    return avail, lscpu
+
+
+def cpu_baseline(name, frames, budget_s=20.0, max_workers=16):
+    """The FP64 CPU oracle on the host cores: one frame per worker process, frames taken in the
+    given order until the time budget is used up (the frames in flight then finish). Workers:
+    the cores this process may run on, at most max_workers (a GPU machine's CPU share for one GPU)."""
+    from concurrent.futures import ProcessPoolExecutor, FIRST_COMPLETED, wait
+    import oracle
+    oracle.build(force=False)
+    avail, lscpu = host_cores()
+    workers = max(1, min(avail, max_workers))
     done, t0 = [], time.perf_counter()
     with ProcessPoolExecutor(max_workers=workers) as ex:
         pending, nxt = {}, 0
-        while nxt < G.shape[0] and len(pending) < workers:
-            pending[ex.submit(_oracle_worker, (N, G[nxt].astype(np.float64)))] = nxt
+        while nxt < len(frames) and len(pending) < workers:
+            pending[ex.submit(_oracle_worker, (name, frames[nxt]))] = frames[nxt]
             nxt += 1
         while pending:
             fin, _ = wait(list(pending), return_when=FIRST_COMPLETED)
             for f in fin:
                 k = pending.pop(f)
                 done.append((k, f.result()))
-                if nxt < G.shape[0] and time.perf_counter() - t0 < budget_s:
-                    pending[ex.submit(_oracle_worker, (N, G[nxt].astype(np.float64)))] = nxt
+                if nxt < len(frames) and time.perf_counter() - t0 < budget_s:
+                    pending[ex.submit(_oracle_worker, (name, frames[nxt]))] = frames[nxt]
                     nxt += 1
     wall = time.perf_counter() - t0
     return {"value": len(done) / wall, "unit": "frames/s", "cores": workers, "kind": "oracle",
-            "sample": f"first {len(done)} frames of the benchmark batch (n=1024, 1.5/2.0/2.5 dB), "
+            "sample": f"{len(done)} frames of the {name} batch taken in turn from its Eb/N0 groups, "
                       f"{workers} worker processes, {wall:.1f} s wall",
-            "single_thread_s_per_frame": float(np.mean([d[1][0] for d in done]))}, done
+            "single_thread_s_per_frame": float(np.mean([d[1][0] for d in done])),
+            "host_cores": {"sched_getaffinity": avail, "lscpu": lscpu, "used": workers}}, done
+
+
+def interleaved_c2(k):
+    """k frames of the n=1024 batch taken in turn from its three Eb/N0 groups."""
+    from synth.workloads import C2_SPLIT
+    starts = np.concatenate([[0], np.cumsum(C2_SPLIT)[:-1]])
+    out = []
+    for r in range(max(C2_SPLIT)):
+        for g0, sz in zip(starts, C2_SPLIT):
+            if r < sz:
+                out.append(int(g0 + r))
+    return out[:k]
 
 
 def plain_fp64(ctx, C, G, frames, budget_s=30.0):
@@ -112,7 +223,7 @@ def plain_fp64(ctx, C, G, frames, budget_s=30.0):
     wall = time.perf_counter() - t0
     return {"value": len(res) / wall, "unit": "frames/s", "frames": len(res),
             "sample": f"{len(res)} frames taken in turn from the 1.5/2.0/2.5 dB groups, lpdec_decode "
-                      f"(FP64 PCG, one frame per launch), {wall:.1f} s"}, res
+                      f"(one frame per launch, host pointers, FP64 PCG, the library's default options), {wall:.1f} s"}, res
 
 
 def log(msg):
@@ -128,20 +239,22 @@ def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
         now = time.perf_counter()
         while t_next <= now:
             ci = int(rng.integers(0, len(codes)))
-            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(stream_id, ci, k))
-            tickets.append((srv.submit(Cs[ci], g), codes[ci].n))
+            e = float(rng.uniform(1.5, 3.0))
+            g = awgn_llr(codes[ci].n, e, 0.5, frame_seed(stream_id, ci, k))
+            tickets.append((srv.submit(Cs[ci], g), codes[ci].n, e, (stream_id, ci, k)))
             k += 1
             t_next += rng.exponential(1.0 / qps)
         time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
     srv.drain()
     wall = time.perf_counter() - t0
     lat, per, fails = [], {}, []
-    for t, n in tickets:
+    for t, n, e, seed in tickets:
         r = srv.poll(t, n)
         lat.append(r[3])
         per.setdefault(n, []).append(r[3])
         if r[1] < 0:
-            fails.append({"n": n, "flag": int(r[1])})
+            # enough to rebuild the frame: awgn_llr(n, ebn0, 0.5, frame_seed(*seed))
+            fails.append({"n": n, "flag": int(r[1]), "ebn0_db": e, "frame_seed": list(seed)})
     lat = np.array(lat)
     return {"offered_qps": qps, "arrival_s": seconds, "requests": len(lat), "frames_per_s": len(lat) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -150,7 +263,7 @@ def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
             "numerical_failures": len(fails), "failure_flags": fails}
 
 
-def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1):
+def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1, burst=384):
     """Frames from a mix of codes, Eb/N0 uniform in [1.5, 3.0] dB, through lpdec_server
     (mode 0: continuous batching over the context's SERVER_STREAMS streams; mode 1: a
     persistent kernel per code that takes each request as a workgroup frees). First the saturated
@@ -173,23 +286,26 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1
     srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
     ctx.set_option("SERVER_MODE", prev)
     try:
-        burst = 384
         t0 = time.perf_counter()
         tk = []
         for k in range(burst):
             ci = int(rng.integers(0, len(codes)))
-            g = awgn_llr(codes[ci].n, float(rng.uniform(1.5, 3.0)), 0.5, frame_seed(78, ci, k))
-            tk.append((srv.submit(Cs[ci], g), codes[ci].n))
+            e = float(rng.uniform(1.5, 3.0))
+            g = awgn_llr(codes[ci].n, e, 0.5, frame_seed(78, ci, k))
+            tk.append((srv.submit(Cs[ci], g), codes[ci].n, e, (78, ci, k)))
         srv.drain()
         sat = burst / (time.perf_counter() - t0)
-        for t, n in tk:
-            srv.poll(t, n)
+        burst_fails = []
+        for t, n, e, seed in tk:
+            r = srv.poll(t, n)
+            if r[1] < 0:
+                burst_fails.append({"n": n, "flag": int(r[1]), "ebn0_db": e, "frame_seed": list(seed)})
         log(f"serving mode {mode}: burst of {burst} at {sat:.0f} frames/s")
         res = _poisson(srv, Cs, codes, rng, qps, seconds, 77)
         log(f"serving mode {mode}: {qps:.0f} qps p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
         res.update({"mode": "persistent" if mode else "waves", "codes": [c.name for c in codes],
                     "streams": int(ctx.get_option("SERVER_STREAMS")) if mode == 0 else len(codes),
-                    "saturated_frames_per_s": sat, "burst": burst,
+                    "saturated_frames_per_s": sat, "burst": burst, "burst_failure_flags": burst_fails,
                     "at_fraction_of_saturated": [dict(fraction=f, **_poisson(srv, Cs, codes, rng, f * sat, seconds,
                                                                                79 + int(10 * f)))
                                                  for f in (0.5, 0.8)]})
@@ -339,21 +455,84 @@ def copy_calibration(dev, nbytes=256 << 20):
     log(f"copy calibration: {nbytes} bytes read and written")
 
 
+def run_leg(ctx, C, g, nf, dev, stream, steps=1, warmup=0, label=""):
+    """Times `steps` launches of the batch with HIP events on the launch stream."""
+    import torch
+    out = ctx.batch_outputs(C, nf, dev)
+    for w in range(warmup):
+        ctx.decode_batch(C, g, out=out, stream=stream)
+        torch.cuda.synchronize()
+        log(f"{label} warmup {w + 1} done")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.decode_batch(C, g, out=out, stream=stream)
+        ev[k + 1].record(stream)
+        ev[k + 1].synchronize()
+        log(f"{label} step {k + 1}: {ev[k].elapsed_time(ev[k + 1]):.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return out, step_ms, wall
+
+
+def leg_summary(name, ctx_opts, code, G, out, step_ms, ncu, elem, traffic=None, traffic_note=None):
+    from paper_0902_0657_amd import stats_table
+    st = stats_table(out["stats"])
+    flags, xhat, objs = out["flag"].cpu().numpy(), out["xhat"].cpu().numpy(), out["obj"].cpu().numpy()
+    nf = G.shape[0]
+    kern_s = float(step_ms.mean()) / 1e3
+    frame_ms = st["ticks_total"].astype(np.float64) / 1e5   # 100 MHz device clock
+    busy = float(frame_ms.sum()) / 1e3
+    return {
+        "value": nf / kern_s, "unit": "frames/s", "ms_per_step": float(step_ms.mean()), "options": ctx_opts,
+        "flags": {str(k): int(v) for k, v in zip(*np.unique(flags, return_counts=True))},
+        "parity_vs_oracle": golden_parity(name, code, G, flags, xhat, objs),
+        "frame_decode_ms": {"p50": float(np.percentile(frame_ms, 50)), "p99": float(np.percentile(frame_ms, 99)),
+                            "max": float(frame_ms.max()), "note": "in-kernel decode time of each frame (device clock)"},
+        "cu_busy_fraction": busy / (kern_s * ncu),
+        "decode_stats": decode_stats(st, nf),
+        "roofline": rooflines(st, code.n, elem, kern_s, ncu, traffic, traffic_note),
+    }, st, flags, xhat, objs
+
+
+def config_leg(name, dev, stream, opts, label):
+    """One launch of a whole workload (c3: n=4096, 256 frames; c4: irregular n=8192, 128
+    frames) with its roofline, parity on the stored oracle frames and decode statistics."""
+    import torch
+    from paper_0902_0657_amd import Code, Context
+    code, G = workload(name)
+    ctx = Context(0, **opts)
+    C = Code.from_synth(ctx, code)
+    g = torch.as_tensor(G, device=dev)
+    out, step_ms, _ = run_leg(ctx, C, g, G.shape[0], dev, stream, 1, 0, f"{name} {label}")
+    elem = 8 if int(ctx.get_option("PRECISION")) != 0 else 4
+    res, *_ = leg_summary(name, opts, code, G, out, step_ms, ctx_ncu(), elem)
+    ctx.close()
+    return res
+
+
+def ctx_ncu():
+    import torch
+    return int(torch.cuda.get_device_properties(0).multi_processor_count)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp64",
-                    help="PCG vector precision of the main leg (fp64: the library's batch default)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="PCG vector precision of the main leg (fp32: the n=1024 workload's FP32-PCG form)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-PCG leg")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--no-pcg-primary", action="store_true",
-                    help="skip the leg with a fixed PCG cap of 500 (dense solves only for systems PCG fails)")
+    ap.add_argument("--no-legs", action="store_true", help="skip the method-only and other-precision legs")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving legs")
     ap.add_argument("--serve-full", action="store_true",
-                    help="serving leg over n = 256, 1024, 4096 and the irregular 8192 code")
+                    help="serving mix over n = 256, 1024, 4096 and the irregular 8192 code")
+    ap.add_argument("--configs", default="", help="comma list of extra whole-workload launches: c3, c4")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB copy first (HBM counter calibration under rocprofv3)")
     ap.add_argument("--block", type=int, default=0)
@@ -361,173 +540,95 @@ def main():
                     help="print the preconditioner comparison of Sec. VI-B (n=2000 code) instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark measures one GPU: frames are independent LPs and the "
-                                   "multi-GPU form is a per-frame shard with no exchange; "
-                                   "run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one GPU's share of the batch); "
+                                   "frames are independent LPs and would shard by frame index with no "
+                                   "exchange: run with --gpus 1"}))
         sys.exit(2)
 
     if args.precond_study:
         print(json.dumps(precond_study()))
         return
     import torch
-    from paper_0902_0657_amd import Code, Context, _lib, stats_table
+    from paper_0902_0657_amd import Code, Context, _lib
     if not os.path.exists(_lib.LIB_PATH):
-        from paper_0902_0657_amd import build as B
-        B.build()
-    code, G = workload()
+        raise SystemExit(f"{_lib.LIB_PATH} is missing: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    code, G = workload("c2")
     dev = torch.device("cuda:0")
+    ncu = ctx_ncu()
     if args.calib_copy:
         copy_calibration(dev)
-    ctx = Context(0)
-    if args.block:
-        ctx.set_option("BLOCK", args.block)
     fp64 = args.precision == "fp64"
-    ctx.set_option("PRECISION", 1 if fp64 else 0)
+    main_opts = {"PRECISION": 1 if fp64 else 0}
+    if args.block:
+        main_opts["BLOCK"] = args.block
+    ctx = Context(0, **main_opts)
     C = Code.from_synth(ctx, code)
     g = torch.as_tensor(G, device=dev)
     stream = torch.cuda.current_stream(dev)
     nf = G.shape[0]
-    out = ctx.batch_outputs(C, nf, dev)
-    for w in range(args.warmup):
-        ctx.decode_batch(C, g, out=out)
-        torch.cuda.synchronize()
-        log(f"warmup {w + 1} done")
-    # HIP events on the stream the decode kernel is launched on
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        ctx.decode_batch(C, g, out=out, stream=stream)
-        ev[k + 1].record(stream)
-        ev[k + 1].synchronize()
-        log(f"step {k + 1}: {ev[k].elapsed_time(ev[k + 1]):.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
-    total_s = float(step_ms.sum()) / 1e3
-    value = nf * args.steps / total_s
-    st = stats_table(out["stats"])
-    flags = out["flag"].cpu().numpy()
-    xhat = out["xhat"].cpu().numpy()
-    objs = out["obj"].cpu().numpy()
-    alg = algorithmic_bytes(st, code.n)
-    kern_s = float(step_ms.mean()) / 1e3
-    achieved = alg / kern_s / 1e9
+    out, step_ms, wall = run_leg(ctx, C, g, nf, dev, stream, args.steps, args.warmup, "main")
     traffic, traffic_note = stored_traffic()
-    frame_ms = st["ticks_total"].astype(np.float64) / 1e5   # 100 MHz device clock
-    flops = dense_flops(st)
-    tf = flops / kern_s / 1e12
-    pcg_share = float(st["ticks_pcg"].sum() / max(1, st["ticks_total"].sum()))
-    dense_share = float(st["ticks_dense"].sum() / max(1, st["ticks_total"].sum()))
-    hbm_view = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": (traffic / 1e9 / kern_s) if traffic is not None else None,
-                "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
-                "algorithmic_bytes_per_launch": alg,
-                "basis": "PCG iterations 27p + 4q bytes, IPM iterations 120q bytes"}
-    mfma_view = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                 "frac": tf / FP64_PEAK_TFS, "traffic": None, "algorithmic_flops_per_launch": flops,
-                 "basis": "dense-fallback Cholesky, P^3/3 flops per solve, FP64 matrix cores"}
-    # the roofline of the work that takes most of the device time; the other one beside it
-    primary, secondary = (mfma_view, hbm_view) if dense_share > pcg_share else (hbm_view, mfma_view)
-    kname = f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>"
-    primary.update({"kernel": kname, "kernel_ms": kern_s * 1e3})
+    main_res, st, flags, xhat, objs = leg_summary("c2", main_opts, code, G, out, step_ms, ncu, 8 if fp64 else 4,
+                                                  traffic, traffic_note)
+    value = main_res["value"]
+    roof = main_res.pop("roofline")
+    roof["kernel"] = f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>"
     res = {
-        "metric": "LP-decoded frames/s at n=1024 (3,6) + p50/p99 latency, vs plain FP64 GPU",
+        "metric": METRIC,
         "value": value, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": float(step_ms.mean()), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if fp64 else "f32 PCG / f64 IPM", "data": "synthetic",
         "config": {"workload": "(3,6)-regular LDPC n=1024 m=512, AWGN Eb/N0 1.5/2.0/2.5 dB "
-                               "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A, "
-                               + ("FP64 PCG" if fp64 else "FP32 PCG") + " (Algorithm 4, Algorithm 7 "
-                               "preconditioner) with FP64 refinement first; once PCG misses its goal within "
-                               "the automatic cap (max(100, p^2/3500) iterations, one round) the LP's remaining Newton systems "
-                               "go to dense FP64 Cholesky on the matrix cores",
+                               "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A; Newton systems "
+                               "by " + ("FP64" if fp64 else "FP32") + " PCG (Algorithm 4, Algorithm 7 "
+                               "preconditioner) with FP64 refinement; a system PCG does not finish within "
+                               "max(100, p^2/3500) iterations, and the rest of its LP's systems, go to a dense "
+                               "FP64 Cholesky on the matrix cores (hybrid; share in decode_stats, the method "
+                               "alone in method_only)",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "batch mode: a frame's result is available when its launch ends"},
-        "frame_decode_ms": {"p50": float(np.percentile(frame_ms, 50)), "p99": float(np.percentile(frame_ms, 99)),
-                            "max": float(frame_ms.max()),
-                            "note": "in-kernel decode time of each frame (device clock)"},
         "wall_s_timed": wall,
-        "decode_stats": {"flags": {str(k): int(v) for k, v in zip(*np.unique(flags, return_counts=True))},
-                         "mean_malp_iters": float(st["malp_iters"].mean()),
-                         "mean_ipm_iters": float(st["ipm_iters"].mean()),
-                         "mean_pcg_iters": float(st["pcg_iters"].mean()),
-                         "mean_pcg_per_newton": float(st["pcg_iters"].sum() / max(1, st["ipm_iters"].sum())),
-                         "max_p": int(st["p_max"].max()), "max_levels": int(st["max_levels"].max()),
-                         "pcg_us_per_iteration": float(st["ticks_pcg"].sum() / 100.0 / max(1, st["pcg_iters"].sum())),
-                         "mts_us_per_ipm_iteration": float(st["ticks_mts"].sum() / 100.0 / max(1, st["ipm_iters"].sum())),
-                         "ref_rounds": int(st["ref_rounds"].sum()),
-                         "dense_fallback_solves": int(st["direct_solves"].sum()),
-                         "newton_solves": int(st["ipm_iters"].sum()),
-                         "newton_solved_by_pcg": 1.0 - float(st["direct_solves"].sum() / max(1, st["ipm_iters"].sum())),
-                         "device_time_share": {"pcg": pcg_share, "dense_fallback": dense_share,
-                                               "mts": float(st["ticks_mts"].sum() / max(1, st["ticks_total"].sum()))}},
-        "roofline": primary,
-        "roofline_other": secondary,
+        "roofline": roof,
+        "main": main_res,
     }
     # serving first among the extra legs, while the process holds no other device work
     if not args.no_serve:
-        res["serving"] = serving(ctx, full=args.serve_full, mode=1)
+        kw = dict(full=True, seconds=4.0, qps=10.0, burst=128) if args.serve_full else {}
+        res["serving"] = serving(ctx, mode=1, **kw)
         log(f"serving: {res['serving']['requests']} requests")
-        res["serving_waves"] = serving(ctx, full=args.serve_full, mode=0)
+        res["serving_waves"] = serving(ctx, mode=0, **kw)
         log(f"serving (waves): {res['serving_waves']['requests']} requests")
-    if not args.no_fp32 and fp64:
-        c32 = Context(0)
-        c32.set_option("PRECISION", 0)
-        C32 = Code.from_synth(c32, code)
-        o32 = c32.batch_outputs(C32, nf, dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        c32.decode_batch(C32, g, out=o32, stream=stream)
-        e1.record(stream)
-        e1.synchronize()
-        ms32 = e0.elapsed_time(e1)
-        f32, x32 = o32["flag"].cpu().numpy(), o32["xhat"].cpu().numpy()
-        res["fp32_pcg"] = {"value": nf / (ms32 / 1e3), "unit": "frames/s", "ms_per_step": ms32,
-                           "flags": {str(k): int(v) for k, v in zip(*np.unique(f32, return_counts=True))},
-                           "differs_from_main": int(sum(1 for f in range(nf) if f32[f] != flags[f]
-                                                        or not np.array_equal(x32[f], xhat[f])))}
-        log(f"fp32 PCG leg: {ms32:.1f} ms")
-        c32.close()
-    if not args.no_pcg_primary:
-        cp = Context(0)
-        cp.set_option("PCG_MAXIT", 500)
-        Cp = Code.from_synth(cp, code)
-        op = cp.batch_outputs(Cp, nf, dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        cp.decode_batch(Cp, g, out=op, stream=stream)
-        e1.record(stream)
-        e1.synchronize()
-        msp = e0.elapsed_time(e1)
-        sp = stats_table(op["stats"])
-        fp_, xp = op["flag"].cpu().numpy(), op["xhat"].cpu().numpy()
-        res["pcg_primary"] = {"value": nf / (msp / 1e3), "unit": "frames/s", "ms_per_step": msp,
-                              "pcg_maxit": 500,
-                              "newton_solved_by_pcg": 1.0 - float(sp["direct_solves"].sum() / max(1, sp["ipm_iters"].sum())),
-                              "differs_from_main": int(sum(1 for f in range(nf) if fp_[f] != flags[f]
-                                                           or not np.array_equal(xp[f], xhat[f])))}
-        log(f"PCG-primary leg: {msp:.1f} ms")
-        cp.close()
+    if not args.no_legs:
+        # the method alone: no dense fallback, FP64 PCG with a fixed cap of 2000 iterations
+        legs = [("method_only", {"DIRECT_FALLBACK": 0, "PCG_MAXIT": 2000, "PRECISION": 1}),
+                ("other_precision", {"PRECISION": 0 if fp64 else 1})]
+        for lname, opts in legs:
+            c2x = Context(0, **opts)
+            Cx = Code.from_synth(c2x, code)
+            ox, msx, _ = run_leg(c2x, Cx, g, nf, dev, stream, 1, 0, lname)
+            res[lname], *_ = leg_summary("c2", opts, code, G, ox, msx, ncu, 8 if opts["PRECISION"] == 1 else 4)
+            log(f"{lname}: {msx.mean():.1f} ms")
+            c2x.close()
+    for name in [c for c in args.configs.split(",") if c]:
+        res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main")
+        log(f"config {name}: {res[f'config_{name}']['ms_per_step']:.0f} ms")
     if not args.no_plain:
-        frames = [g0 + k for k in range(8) for g0 in (0, 171, 342)]
+        frames = interleaved_c2(24)
         pf, plain_res = plain_fp64(ctx, C, G, frames)
         log(f"plain FP64: {pf['frames']} frames")
         res["plain_fp64"] = pf
         res["speedup_vs_plain"] = value / pf["value"]
-        mism = [f for f, xh, fl, ob in plain_res if not (np.array_equal(xh, xhat[f]) and fl == flags[f])]
-        res["plain_fp64"]["mismatch_vs_batch"] = len(mism)
+        res["plain_fp64"]["mismatch_vs_batch"] = len([f for f, xh, fl, ob in plain_res
+                                                      if not (np.array_equal(xh, xhat[f]) and fl == flags[f])])
     if not args.no_cpu:
-        cb, done = cpu_baseline(G)
+        cb, done = cpu_baseline("c2", interleaved_c2(nf))
         log(f"cpu baseline: {len(done)} frames")
         res["cpu_baseline"] = cb
         mism = [k for k, (t, xh, fl, ob) in done
                 if not (np.array_equal(xh, xhat[k]) and fl == flags[k]
                         and abs(ob - objs[k]) <= 1e-6 * (1.0 + abs(ob - float(G[k][G[k] < 0].sum()))))]
-        res["parity_sample"] = {"frames": len(done), "mismatches": len(mism)}
+        res["cpu_baseline"]["mismatches_vs_main"] = len(mism)
     print(json.dumps(res))
 
 

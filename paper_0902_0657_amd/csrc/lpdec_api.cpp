@@ -70,7 +70,8 @@ struct lpdec_ctx {
 };
 
 struct lpdec_code {
-    lpdec_ctx *ctx = nullptr;
+    lpdec_ctx *ctx = nullptr;   // compared only: the context may be destroyed before the code
+    int device = 0;             // the device holding the code's arrays
     int m = 0, n = 0, E = 0, dcmax = 0, dvmax = 0;
     int *d_rowptr = nullptr, *d_col = nullptr, *d_colptr = nullptr, *d_vlist = nullptr;
     std::vector<int> rowptr, col;
@@ -343,7 +344,7 @@ extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, 
     const int E = rowptr[m];
     auto *c = new (std::nothrow) lpdec_code();
     if (!c) return LPDEC_ENOMEM;
-    c->ctx = ctx; c->m = m; c->n = n; c->E = E; c->dcmax = dcmax;
+    c->ctx = ctx; c->device = ctx->device; c->m = m; c->n = n; c->E = E; c->dcmax = dcmax;
     c->rowptr.assign(rowptr, rowptr + m + 1);
     c->col.assign(col, col + E);
     std::vector<int> colptr(n + 1, 0), vlist(E);
@@ -378,7 +379,7 @@ extern "C" lpdec_status lpdec_code_create(lpdec_ctx *ctx, int32_t m, int32_t n, 
 extern "C" lpdec_status lpdec_code_destroy(lpdec_code *c)
 {
     if (!c) return LPDEC_EINVAL;
-    if (c->ctx) (void)hipSetDevice(c->ctx->device);
+    (void)hipSetDevice(c->device);
     if (c->d_rowptr) (void)hipFree(c->d_rowptr);
     if (c->d_col) (void)hipFree(c->d_col);
     if (c->d_colptr) (void)hipFree(c->d_colptr);

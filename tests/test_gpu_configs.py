@@ -93,3 +93,21 @@ def test_c2_n1024_all_frames(ctx, precision):
     fl = host(out["flag"])
     print(f"[c2] precision {precision}: {int((fl == 1).sum())} integral, {int((fl == 0).sum())} fractional, "
           f"0 mismatches", flush=True)
+
+
+def test_c3_n4096_full_launch(ctx):
+    code, G, out = _launch(ctx, "c3")
+    _invariants(code, out)
+    gold = _golden("c3")
+    assert {r["flag"] for r in gold.values()} >= {0, 1}   # integral and fractional frames
+    bad = _against_golden(code, G, out, gold)
+    assert not bad, bad
+
+
+def test_c4_irregular_n8192_full_launch(ctx):
+    """Every frame of this batch decodes integral (BSC p=0.04 is below the code's LP threshold);
+    the stored frames include the ones whose hard decisions violate the most checks."""
+    code, G, out = _launch(ctx, "c4")
+    _invariants(code, out)
+    bad = _against_golden(code, G, out, _golden("c4"))
+    assert not bad, bad
