@@ -216,6 +216,24 @@ lpdec_status lpdec_decode_batch_trace(lpdec_ctx *ctx, const lpdec_code *code, in
                                       lpdec_stats *stats_dev, double *u_dev,
                                       uint32_t *trace_dev, int32_t trace_cap);
 
+/* Same as lpdec_decode_batch, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that forbid allocation): the call allocates nothing. Its
+ * workspace is a fixed device region of LPDEC_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per device, set up by lpdec_ctx_create and held until the process ends. A batch runs as a
+ * resident set of workgroups that take the frames in turn, as many as the region holds
+ * arenas for (at most as many as the device holds at once), so any nframes fits; results are
+ * bit-identical to lpdec_decode_batch with the same options. Returns LPDEC_EINVAL when one
+ * frame's workspace (plus the batch's ordering arrays, 8 bytes per frame) exceeds the region,
+ * e.g. the irregular n=8192 code with DIRECT_FALLBACK 1 (its dense system alone is 134 MB).
+ * Every call on a device shares that device's region and leaves its contents behind: calls
+ * that overlap on one device (on different streams or contexts, or from different host
+ * threads) race. */
+#define LPDEC_NOALLOC_SCRATCH_BYTES (128u << 20)
+lpdec_status lpdec_decode_batch_noalloc(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                        const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
+                                        int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,
+                                        double *u_dev, void *stream);
+
 /* ---- steps of the hot path, one frame per workgroup, device pointers, synchronous ----- */
 /* Algorithm 2 on every check at the points u_dev (double[nframes*n]):
  * vmask_dev uint32[nframes*m] = V of the check's minimising odd set, viol_dev uint8[nframes*m]

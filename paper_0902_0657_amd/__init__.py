@@ -109,9 +109,12 @@ class Context:
             out["u"] = torch.empty((nf, code.n), dtype=torch.float64, device=device)
         return out
 
-    def decode_batch(self, code: "Code", gamma, out=None, want_u=False, want_stats=True, stream=None):
+    def decode_batch(self, code: "Code", gamma, out=None, want_u=False, want_stats=True, stream=None,
+                     noalloc=False):
         """gamma: CUDA tensor [nframes, n] (float32 or float64). Asynchronous on `stream`
-        (default: torch's current stream). Returns a dict of output tensors."""
+        (default: torch's current stream). Returns a dict of output tensors. noalloc=True calls
+        lpdec_decode_batch_noalloc (the library's fixed device region as workspace; pass `out`
+        to allocate nothing here either)."""
         import torch
         assert gamma.is_cuda and gamma.is_contiguous() and gamma.dim() == 2 and gamma.shape[1] == code.n
         nf = gamma.shape[0]
@@ -121,7 +124,8 @@ class Context:
         gdt = 1 if gamma.dtype == torch.float64 else 0
         assert gamma.dtype in (torch.float32, torch.float64)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
-        self._check(self.L.lpdec_decode_batch(self.h, code.h, nf, _ptr(gamma), gdt, _ptr(out["xhat"]),
+        fn = self.L.lpdec_decode_batch_noalloc if noalloc else self.L.lpdec_decode_batch
+        self._check(fn(self.h, code.h, nf, _ptr(gamma), gdt, _ptr(out["xhat"]),
                                               _ptr(out["flag"]), _ptr(out.get("obj")), _ptr(out.get("stats")),
                                               _ptr(out.get("u")), C.c_void_p(s.cuda_stream)))
         return out

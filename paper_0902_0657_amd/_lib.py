@@ -43,6 +43,7 @@ _SIGS = {
     "lpdec_code_destroy": (_I, [_P]),
     "lpdec_decode": (_I, [_P, _P, _P, _P, C.POINTER(_I), C.POINTER(_D), C.POINTER(Stats), _P]),
     "lpdec_decode_batch": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P]),
+    "lpdec_decode_batch_noalloc": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P]),
     "lpdec_decode_batch_trace": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _I]),
     "lpdec_cut_search_batch": (_I, [_P, _P, _I, _P, _P, _P, _P]),
     "lpdec_mts_batch": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P]),

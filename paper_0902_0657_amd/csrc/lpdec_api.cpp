@@ -28,11 +28,13 @@ namespace {
 struct Workspace {
     char *ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;   // a region the library may not grow (the allocation-free entry point)
 };
 
 hipError_t ws_ensure(Workspace &w, size_t bytes)
 {
     if (bytes <= w.bytes) return hipSuccess;
+    if (w.fixed) return hipErrorOutOfMemory;
     if (w.ptr) {
         hipError_t e = hipFree(w.ptr);
         if (e != hipSuccess) return e;
@@ -67,6 +69,7 @@ struct lpdec_ctx {
     int dispatch_order = 1;
     std::string err;
     Workspace ws;
+    char *scratch = nullptr;   // the device's fixed region of lpdec_decode_batch_noalloc
 };
 
 struct lpdec_code {
@@ -168,10 +171,22 @@ lpdec_status launch(lpdec_ctx *ctx, const lpdec_code *code, Args &a, int pt64, W
         const long long cap = (long long)lpdec::decode_per_cu(pt64, a.hot_in_lds, block, lds_launch) * ctx->ncu;
         if (a.nframes > cap) grid = (int)cap;
     }
+    const size_t nf4 = lpdec::lp_align(4 * (size_t)a.nframes);
+    const size_t ord_full = 2 * nf4 + lpdec::lp_align(4 * ((size_t)code->m + 1));
+    if (ws.fixed) {
+        // a region that cannot grow holds as many arenas as fit beside the claim counter and
+        // the ordering arrays; the rest of the frames are taken in turn
+        if (a.mode != lpdec::MODE_DECODE) return fail(ctx, LPDEC_EINVAL, "fixed workspace is for decoding only");
+        const size_t extra_max = ord_full + 256;
+        const size_t fit = ws.bytes > extra_max ? (ws.bytes - extra_max) / per : 0;
+        if (fit < 1)
+            return fail(ctx, LPDEC_EINVAL, "one frame's workspace (%zu bytes) and the ordering arrays (%zu bytes) "
+                        "exceed the fixed region of %zu bytes", per, extra_max, ws.bytes);
+        if ((size_t)grid > fit) grid = (int)fit;
+    }
     const bool claimed = grid < a.nframes;
     const bool ordered = claimed && ctx->dispatch_order;
-    const size_t nf4 = lpdec::lp_align(4 * (size_t)a.nframes);
-    const size_t ord_bytes = ordered ? 2 * nf4 + lpdec::lp_align(4 * ((size_t)code->m + 1)) : 0;
+    const size_t ord_bytes = ordered ? ord_full : 0;
     const size_t extra = ord_bytes + (claimed ? 256 : 0);
     hipError_t e = ws_ensure(ws, per * (size_t)grid + extra);
     if (e != hipSuccess) return hipfail(ctx, e, "workspace allocation");
@@ -228,6 +243,12 @@ extern "C" lpdec_status lpdec_ctx_create(int device, lpdec_ctx **out)
         c->lds_limit = lds;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->ncu = ncu;
+    // the device address of the allocation-free entry point's region (looked up once per
+    // device); a failure here only disables that entry point
+    if (lpdec::scratch_region(device, &c->scratch) != hipSuccess) {
+        c->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     *out = c;
     return LPDEC_OK;
 }
@@ -417,6 +438,22 @@ extern "C" lpdec_status lpdec_decode_batch(lpdec_ctx *ctx, const lpdec_code *cod
     if (st) return st;
     return decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev,
                              stats_dev, u_dev, nullptr, 0, precision_for(ctx, 1), ctx->ws, (hipStream_t)stream);
+}
+
+extern "C" lpdec_status lpdec_decode_batch_noalloc(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                                   const void *gamma_dev, int32_t gamma_dtype, uint8_t *xhat_dev,
+                                                   int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,
+                                                   double *u_dev, void *stream)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (!ctx->scratch) return fail(ctx, LPDEC_EDEVICE, "the fixed device region was not found at context creation");
+    Workspace fixed;
+    fixed.ptr = ctx->scratch;
+    fixed.bytes = lpdec::kScratchBytes;
+    fixed.fixed = true;
+    return decode_batch_impl(ctx, code, nframes, gamma_dev, gamma_dtype, xhat_dev, flag_dev, obj_dev,
+                             stats_dev, u_dev, nullptr, 0, precision_for(ctx, 1), fixed, (hipStream_t)stream);
 }
 
 extern "C" lpdec_status lpdec_decode_batch_trace(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,

@@ -4,6 +4,8 @@
 // compiler emits LDS instructions for the LDS instantiation.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lpdec_device.hpp"
 #include "lpdec_launch.hpp"
 
@@ -384,6 +386,30 @@ int decode_per_cu(int pt64, int hot_in_lds, int block, size_t lds_bytes)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds_bytes) != hipSuccess || nb < 1) nb = 1;
     (void)hipGetLastError();
     return nb;
+}
+
+// Workspace of lpdec_decode_batch_noalloc: a fixed region of device memory that every call on
+// a device shares (each device holds its own copy from the load of the library's code object
+// until the process ends). Host code must not pass the symbol itself to a kernel: its name
+// there is a host-side stand-in, not a device address. scratch_region looks the device address
+// up once per device and hands out that address only.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+hipError_t scratch_region(int device, char **ptr)
+{
+    static std::mutex mu;
+    static char *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        char *p = nullptr;
+        // the caller has made `device` current
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_clear(int32_t *p, int n, hipStream_t stream)

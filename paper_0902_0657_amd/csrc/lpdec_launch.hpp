@@ -13,6 +13,13 @@ hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hip
 int decode_per_cu(int pt64, int hot_in_lds, int block, size_t lds_bytes);
 // Zeroes n ints on `stream` with a kernel (no memset node when the stream is captured).
 hipError_t launch_clear(int32_t *p, int n, hipStream_t stream);
+// Size of the fixed device region behind lpdec_decode_batch_noalloc, and the devices it is
+// looked up for.
+constexpr size_t kScratchBytes = (size_t)LPDEC_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+// Device address of that region on `device` (which must be current); looked up with
+// hipGetSymbolAddress on the first call per device.
+hipError_t scratch_region(int device, char **ptr);
 // Static LDS used by the kernel besides the hot arena.
 size_t static_lds_bytes();
 // Dispatch order of a decode batch (a.nframes frames of a.gamma): order[0..nframes) lists the
