@@ -6,6 +6,16 @@
 
 namespace lpdec {
 
+// The four instantiations of the decode kernels (lpdec_inst_*.hip): launchers for every mode,
+// and the address of the MODE_DECODE kernel (for occupancy queries).
+hipError_t launch_f64_lds(const Args &a, int block, size_t lds, hipStream_t s, int grid);
+hipError_t launch_f64_glb(const Args &a, int block, size_t lds, hipStream_t s, int grid);
+hipError_t launch_f32_lds(const Args &a, int block, size_t lds, hipStream_t s, int grid);
+hipError_t launch_f32_glb(const Args &a, int block, size_t lds, hipStream_t s, int grid);
+const void *decode_kernel_f64_lds();
+const void *decode_kernel_f64_glb();
+const void *decode_kernel_f32_lds();
+const void *decode_kernel_f32_glb();
 // Launches one workgroup per frame. pt64: PCG in FP64 (1) or FP32 (0). lds_bytes: dynamic
 // LDS for the hot arena when a.hot_in_lds.
 hipError_t launch_main(const Args &a, int pt64, int block, size_t lds_bytes, hipStream_t stream, int grid);
