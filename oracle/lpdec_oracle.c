@@ -19,6 +19,7 @@
  *     the binary heap of Sec. V-B, and the dependency levels of the two triangular solves.
  *   - Algorithm 8 (row-wise greedy search) with the diagonal or the triangular expansion of
  *     Sec. V-B, and the levels of any triangular set.
+ *   - Algorithm 6 (incremental greedy search) with the Triangulation Step of Algorithm 5.
  *   - Algorithm 4 (PCG) in FP64 with the preconditioner M = A_M D_M^2 A_M^T of Sec. V,
  *     used only as a reference in tests (the decoder itself uses Cholesky).
  *
@@ -764,6 +765,94 @@ int orc_mts_row2(int m, int n, const int *rowptr, const int *col, const uint8_t 
         if (hascut[j] && pair[j] < 0) { pair[j] = n + j; order[k++] = j; }
     free(alive); free(rdeg);
     colview_free(&cv);
+    return k;
+}
+
+/* Algorithm 5 (Triangulation Step) on a column set S of the LP's A (inS[c] != 0; c < n a    */
+/* standard column, c = n + j the slack of check j, which must carry a cut). Peeling: a row    */
+/* with exactly one remaining column of S is matched with it, and that column leaves; A_S     */
+/* is lower triangular in matching order. The paper lets any degree-1 row go next; here the   */
+/* peeling runs in rounds: the rows of degree 1 at the start of a round, in ascending order,  */
+/* each take their column unless an earlier row of the round has taken it. Rows that reach    */
+/* degree 1 during a round wait for the next one. Success iff every column of S is matched:  */
+/* returns the number matched; pair[j] = column of row j (-1 unmatched), order[k] = row      */
+/* matched k-th.                                                                             */
+int orc_triangulate(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                    const uint8_t *inS, int *pair, int *order)
+{
+    colview cv;
+    colview_build(&cv, m, n, rowptr, col, hascut);
+    int *rdeg = calloc(m, sizeof(int));
+    uint8_t *gone = calloc(n + m, 1);          /* column of S already matched */
+    int *round_rows = malloc(sizeof(int) * (m + 1));
+    int s = 0, k = 0;
+    for (int c = 0; c < n + m; ++c) s += inS[c] != 0;
+    for (int j = 0; j < m; ++j) {
+        pair[j] = -1;
+        if (!hascut[j]) continue;
+        int d = inS[n + j] ? 1 : 0;
+        for (int t = rowptr[j]; t < rowptr[j + 1]; ++t) d += inS[col[t]] != 0;
+        rdeg[j] = d;
+    }
+    for (;;) {
+        int nr = 0;
+        for (int j = 0; j < m; ++j)
+            if (hascut[j] && pair[j] < 0 && rdeg[j] == 1) round_rows[nr++] = j;
+        if (nr == 0) break;
+        for (int a = 0; a < nr; ++a) {
+            int j = round_rows[a], c = -1;
+            if (inS[n + j] && !gone[n + j]) c = n + j;
+            for (int t = rowptr[j]; t < rowptr[j + 1]; ++t)
+                if (inS[col[t]] && !gone[col[t]]) c = col[t];
+            if (c < 0) continue;                  /* its column went to an earlier row */
+            pair[j] = c;
+            order[k++] = j;
+            gone[c] = 1;
+            if (c >= n) rdeg[c - n]--;
+            else
+                for (int t = cv.cptr[c]; t < cv.cptr[c + 1]; ++t) rdeg[cv.crow[t]]--;
+        }
+    }
+    free(rdeg); free(gone); free(round_rows);
+    colview_free(&cv);
+    (void)s;
+    return k;
+}
+
+/* Algorithm 6: incremental greedy search for the triangular set. The LP's columns (all n    */
+/* standard columns and the slack of every check with a cut) in the order of the key (w      */
+/* descending, then column index ascending); each is added to M when M with it still passes  */
+/* the Triangulation Step, until M has p columns. The pairing and order are those of the     */
+/* Triangulation Step on the final M (A_M lower triangular in that order). Returns p.        */
+typedef struct { float w; int idx; } ckey;
+
+static int ckey_cmp(const void *a, const void *b)
+{
+    const ckey *x = a, *y = b;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1;
+    return x->idx - y->idx;
+}
+
+int orc_mts_inc(int m, int n, const int *rowptr, const int *col, const uint8_t *hascut,
+                const float *w, int *pair, int *order, int *calls)
+{
+    int p = 0, q = 0;
+    for (int j = 0; j < m; ++j) p += hascut[j] != 0;
+    ckey *keys = malloc(sizeof(ckey) * (n + m + 1));
+    for (int c = 0; c < n + m; ++c)
+        if (c < n || hascut[c - n]) { keys[q].w = w[c]; keys[q].idx = c; ++q; }
+    qsort(keys, q, sizeof(ckey), ckey_cmp);
+    uint8_t *inS = calloc(n + m, 1);
+    int msz = 0, nc = 0;
+    for (int t = 0; t < q && msz < p; ++t) {
+        inS[keys[t].idx] = 1;
+        ++nc;
+        if (orc_triangulate(m, n, rowptr, col, hascut, inS, pair, order) == msz + 1) ++msz;
+        else inS[keys[t].idx] = 0;
+    }
+    int k = orc_triangulate(m, n, rowptr, col, hascut, inS, pair, order);
+    if (calls) *calls = nc + 1;
+    free(keys); free(inS);
     return k;
 }
 

@@ -242,3 +242,29 @@ def normal_solve(code, gamma, mask, d2, w):
     _L().orc_normal_solve(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
                           _p(gamma), _p(mask), _p(_f64(d2)), _p(_f64(w)), _p(y))
     return y
+
+
+def triangulate(code, hascut, inS):
+    """Algorithm 5 (Triangulation Step) on the column set inS (n+m flags, slack of check j at
+    n+j). Returns (matched, pair[m], order[matched]); success iff matched == inS.sum()."""
+    hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
+    inS = np.ascontiguousarray(inS, dtype=np.uint8)
+    pair = np.full(code.m, -1, dtype=np.int32)
+    order = np.zeros(code.m + 1, dtype=np.int32)
+    k = _L().orc_triangulate(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
+                             _p(hascut), _p(inS), _p(pair), _p(order))
+    return int(k), pair, order[:k]
+
+
+def mts_inc(code, hascut, w):
+    """Algorithm 6 (incremental greedy search) with Algorithm 5. w: float32 weights, n+m
+    entries. Returns (pair[m], order[p], triangulation calls); A_M is lower triangular in
+    that order."""
+    hascut = np.ascontiguousarray(hascut, dtype=np.uint8)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    pair = np.full(code.m, -1, dtype=np.int32)
+    order = np.zeros(code.m + 1, dtype=np.int32)
+    calls = C.c_int(0)
+    p = _L().orc_mts_inc(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
+                         _p(hascut), _p(w), _p(pair), _p(order), C.byref(calls))
+    return pair, order[:p], int(calls.value)

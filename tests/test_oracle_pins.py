@@ -700,3 +700,129 @@ def test_malp_sweep_no_failures(orc, n, mode, frames):
     assert min(r[3] for r in res) > -1e-8
     assert min(r[4] for r in res) >= 0.0 and max(r[5] for r in res) <= 1.0
     assert sum(r[2] == 0 for r in res) > frames // 50       # the sweep reaches fractional frames
+
+
+# ---------------------------------------------------------------- Algorithm 5 + Algorithm 6
+def _lp_pattern(code, hascut):
+    """Nonzero pattern of the LP's A as a code: rows = checks with a cut, columns = the n
+    standard columns and the slack column n+j of every such check (zero columns elsewhere)."""
+    H = code.dense()
+    rows = np.nonzero(hascut)[0]
+    A = np.zeros((len(rows), code.n + code.m), dtype=np.uint8)
+    for r, j in enumerate(rows):
+        A[r, :code.n] = H[j]
+        A[r, code.n + j] = 1
+    return A
+
+
+def _triangulable(A, S):
+    """Algorithm 5 read from the paper on an explicit matrix: s times, some row with exactly one
+    remaining column of S gives up that column (row and column zeroed); failure when no such
+    row exists."""
+    sub = A[:, S].astype(bool).copy()
+    for _ in range(len(S)):
+        deg = sub.sum(axis=1)
+        r = np.nonzero(deg == 1)[0]
+        if r.size == 0:
+            return False
+        i = int(np.nonzero(sub[r[0]])[0][0])
+        sub[:, i] = False
+        sub[r[0], :] = False
+    return True
+
+
+def _check_lower_triangular(code, hascut, inS, pair, order):
+    """A_S in matching order: the columns of S in the k-th matched row are matched at or
+    before position k, and the diagonal entries are nonzero."""
+    A = _lp_pattern(code, hascut)
+    rowpos = {int(j): r for r, j in enumerate(np.nonzero(hascut)[0])}
+    pos = {int(pair[j]): k for k, j in enumerate(order)}
+    assert len(pos) == len(order)
+    for k, j in enumerate(order):
+        a = A[rowpos[int(j)]]
+        assert a[pair[j]]
+        for c in np.nonzero(a)[0]:
+            if inS[c]:
+                assert pos[int(c)] <= k
+
+
+def test_triangulation_step_is_peeling_and_triangulates(orc):
+    """Algorithm 5 succeeds exactly when the column set holds no stopping set of the LP's
+    extended Tanner graph (brute force), agrees with the explicit-matrix reading, and its
+    pairing puts A_S in lower-triangular form."""
+    from synth.codes import from_dense
+    rng = np.random.Generator(np.random.PCG64(61))
+    ok = fail = 0
+    for n in (12, 16):
+        code = regular_code(n, no4=False)
+        for _ in range(60):
+            hascut = (rng.random(code.m) < 0.8).astype(np.uint8)
+            if not hascut.any():
+                continue
+            A = _lp_pattern(code, hascut)
+            present = [c for c in range(code.n + code.m) if c < code.n or hascut[c - code.n]]
+            S = sorted(rng.choice(present, size=int(rng.integers(1, min(9, len(present)) + 1)), replace=False).tolist())
+            inS = np.zeros(code.n + code.m, np.uint8)
+            inS[S] = 1
+            k, pair, order = orc.triangulate(code, hascut, inS)
+            succ = k == len(S)
+            ext = from_dense(A)
+            assert succ == _triangulable(A, S) == (not refs.has_stopping_set(ext, inS))
+            if succ:
+                ok += 1
+                assert sorted(int(pair[j]) for j in order) == S
+                _check_lower_triangular(code, hascut, inS, pair, order)
+            else:
+                fail += 1
+    assert ok > 20 and fail > 20
+
+
+def _mts_inc_dense(code, hascut, w):
+    """Algorithm 6 read from the paper: columns by weight descending (index ascending on ties),
+    each added while the set still passes the Triangulation Step, until p are chosen."""
+    A = _lp_pattern(code, hascut)
+    p = int(hascut.sum())
+    cols = [c for c in range(code.n + code.m) if c < code.n or hascut[c - code.n]]
+    cols.sort(key=lambda c: (-np.float32(w[c]), c))
+    M = []
+    for c in cols:
+        if len(M) == p:
+            break
+        if _triangulable(A, M + [c]):
+            M.append(c)
+    return sorted(M)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "ties", "spread"])
+def test_mts_inc_equals_dense_replay(orc, kind):
+    rng = np.random.Generator(np.random.PCG64(62))
+    for n in (48, 96):
+        code = regular_code(n) if n >= 60 else regular_code(n, no4=False)
+        for _ in range(4):
+            hascut = (rng.random(code.m) < 0.8).astype(np.uint8)
+            w = _weights(rng, code.n + code.m, kind)
+            pair, order, calls = orc.mts_inc(code, hascut, w)
+            p = int(hascut.sum())
+            assert len(order) == p
+            assert sorted(int(pair[j]) for j in order) == _mts_inc_dense(code, hascut, w)
+            inS = np.zeros(code.n + code.m, np.uint8)
+            inS[[int(pair[j]) for j in order]] = 1
+            _check_lower_triangular(code, hascut, inS, pair, order)
+            assert calls >= p
+
+
+def test_mts_inc_closed_forms(orc):
+    """Slack columns heavier than every standard column: M is the slack set (A_M = I). One
+    check: M is its heaviest column."""
+    code = regular_code(96)
+    rng = np.random.Generator(np.random.PCG64(63))
+    hascut = (rng.random(code.m) < 0.7).astype(np.uint8)
+    w = np.concatenate([rng.random(code.n), 2.0 + rng.random(code.m)]).astype(np.float32)
+    pair, order, _ = orc.mts_inc(code, hascut, w)
+    assert all(pair[j] == code.n + j for j in np.nonzero(hascut)[0])
+    one = np.zeros(code.m, np.uint8)
+    one[5] = 1
+    w = rng.random(code.n + code.m).astype(np.float32)
+    pair, order, _ = orc.mts_inc(code, one, w)
+    cand = list(code.row(5)) + [code.n + 5]
+    assert pair[5] == max(cand, key=lambda c: (np.float32(w[c]), -c))
