@@ -20,6 +20,7 @@
  *   - Algorithm 8 (row-wise greedy search) with the diagonal or the triangular expansion of
  *     Sec. V-B, and the levels of any triangular set.
  *   - Algorithm 6 (incremental greedy search) with the Triangulation Step of Algorithm 5.
+ *   - ALP decoding (Algorithm 1): all cuts kept, several per check possible.
  *   - Algorithm 4 (PCG) in FP64 with the preconditioner M = A_M D_M^2 A_M^T of Sec. V,
  *     used only as a reference in tests (the decoder itself uses Cholesky).
  *
@@ -115,13 +116,15 @@ static void lp_free(lp_t *lp)
     memset(lp, 0, sizeof(*lp));
 }
 
-/* sigma_i = +1 when gamma_i >= 0 (the box constraint u_i >= 0 is kept), else -1. */
-static void lp_build(lp_t *lp, int m, int n, const int *rowptr, const int *col,
-                     const double *gamma, const uint32_t *mask)
+/* The LP of a list of cuts: cut r comes from check chk[r] with odd set V[r] (bit k = k-th
+   neighbour of the check). sigma_i = +1 when gamma_i >= 0 (the box constraint u_i >= 0 is
+   kept), else -1. MALP's LPs list at most one cut per check, in ascending check order; ALP's
+   can hold several cuts of one check. */
+static void lp_build_cuts(lp_t *lp, int n, const int *rowptr, const int *col, const double *gamma,
+                          int p, const int *chk, const uint32_t *Vs)
 {
-    int p = 0, nnz = 0;
-    for (int j = 0; j < m; ++j)
-        if (mask[j]) { ++p; nnz += rowptr[j + 1] - rowptr[j]; }
+    int nnz = 0;
+    for (int r = 0; r < p; ++r) nnz += rowptr[chk[r] + 1] - rowptr[chk[r]];
     lp->n = n; lp->p = p; lp->q = n + p;
     lp->rowchk = malloc(sizeof(int) * (p + 1));
     lp->rptr = malloc(sizeof(int) * (p + 1));
@@ -129,30 +132,27 @@ static void lp_build(lp_t *lp, int m, int n, const int *rowptr, const int *col,
     lp->rval = malloc(nnz + 1);
     lp->b = malloc(sizeof(double) * (p + 1));
     lp->c = malloc(sizeof(double) * (n + p + 1));
-    int r = 0, e = 0;
+    int e = 0;
     lp->rptr[0] = 0;
-    for (int j = 0; j < m; ++j) {
-        if (!mask[j]) continue;
-        uint32_t V = mask[j];
+    for (int r = 0; r < p; ++r) {
+        const int j = chk[r];
+        uint32_t V = Vs[r];
         int vsz = 0;
-        double bb;
         int sneg = 0;
         for (int t = rowptr[j]; t < rowptr[j + 1]; ++t) {
             int k = t - rowptr[j];
             int i = col[t];
-            int s = ((V >> k) & 1u) ? 1 : -1;      /* coefficient of u_i in A u <= b */
+            int sv = ((V >> k) & 1u) ? 1 : -1;     /* coefficient of u_i in A u <= b */
             int sig = gamma[i] >= 0.0 ? 1 : -1;
             if ((V >> k) & 1u) ++vsz;
-            if (sig < 0) sneg += s;                  /* u_i = 1 - x_i moves s to the rhs */
+            if (sig < 0) sneg += sv;                 /* u_i = 1 - x_i moves sv to the rhs */
             lp->ridx[e] = i;
-            lp->rval[e] = (signed char)(sig * s);
+            lp->rval[e] = (signed char)(sig * sv);
             ++e;
         }
-        bb = (double)(vsz - 1) - (double)sneg;
         lp->rowchk[r] = j;
-        lp->b[r] = bb;
-        ++r;
-        lp->rptr[r] = e;
+        lp->b[r] = (double)(vsz - 1) - (double)sneg;
+        lp->rptr[r + 1] = e;
     }
     for (int i = 0; i < n; ++i) lp->c[i] = fabs(gamma[i]);
     for (int k = 0; k < p; ++k) lp->c[n + k] = 0.0;
@@ -172,6 +172,21 @@ static void lp_build(lp_t *lp, int m, int n, const int *rowptr, const int *col,
             fill[i]++;
         }
     free(fill);
+}
+
+/* The LP of a cut set with at most one cut per check: mask[j] = V of check j's cut, 0 = none. */
+static void lp_build(lp_t *lp, int m, int n, const int *rowptr, const int *col,
+                     const double *gamma, const uint32_t *mask)
+{
+    int p = 0;
+    for (int j = 0; j < m; ++j) p += mask[j] != 0;
+    int *chk = malloc(sizeof(int) * (p + 1));
+    uint32_t *Vs = malloc(sizeof(uint32_t) * (p + 1));
+    p = 0;
+    for (int j = 0; j < m; ++j)
+        if (mask[j]) { chk[p] = j; Vs[p] = mask[j]; ++p; }
+    lp_build_cuts(lp, n, rowptr, col, gamma, p, chk, Vs);
+    free(chk); free(Vs);
 }
 
 /* y = A x  (length p) */
@@ -440,6 +455,111 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
     if (st) *st = s;
     free(mask); free(active); free(u); free(nb); free(x); free(z); free(y);
     return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* ALP decoding (Algorithm 1): every LP keeps all cuts added so far; each iteration adds the  */
+/* (at most one per check, Theorem 1) violated parity inequality of every check at the last  */
+/* solution, found by Algorithm 2; box constraints are not searched (Theorem 2a). New cuts of */
+/* an iteration follow the existing ones, in ascending check order. Same output, flags and   */
+/* readings (box clamp, cost check) as orc_decode. trace_p[k] / trace_obj[k] / trace_ipm[k]: */
+/* cuts, cost and IPM iterations of the k-th LP. cuts_out (optional, cap entries of          */
+/* (check, V) pairs, 2 ints each) receives the final cut list; returns the number of cuts.    */
+int orc_alp_decode(int m, int n, const int *rowptr, const int *col, const double *gamma,
+                   const orc_opts *o, double *u_out, uint8_t *xhat, int *flag, double *obj,
+                   orc_stats *st, double *trace_obj, int *trace_p, int *trace_ipm, int trace_cap,
+                   int *cuts_out, int cuts_cap)
+{
+    int cap = 16 * m + 16, p = 0;
+    int *chk = malloc(sizeof(int) * cap);
+    uint32_t *Vs = malloc(sizeof(uint32_t) * cap);
+    double *u = malloc(sizeof(double) * n);
+    double *nb = malloc(sizeof(double) * 64);
+    double *x = NULL, *z = NULL, *y = NULL;
+    orc_stats s = {0, 0, 0, 0, 0};
+    double gneg = 0.0;
+    for (int i = 0; i < n; ++i) {
+        u[i] = gamma[i] >= 0.0 ? 0.0 : 1.0;
+        if (gamma[i] < 0.0) gneg += gamma[i];
+    }
+    double cost_prev = gneg;
+    int k;
+    for (k = 0; k < o->malp_max; ++k) {
+        int added = 0;
+        for (int j = 0; j < m; ++j) {
+            int d = rowptr[j + 1] - rowptr[j];
+            for (int t = 0; t < d; ++t) nb[t] = u[col[rowptr[j] + t]];
+            uint32_t V;
+            double lhs;
+            if (orc_find_cut(d, nb, o->tau_viol, &V, &lhs)) {
+                if (p == cap) {
+                    cap *= 2;
+                    chk = realloc(chk, sizeof(int) * cap);
+                    Vs = realloc(Vs, sizeof(uint32_t) * cap);
+                }
+                chk[p] = j;
+                Vs[p] = V;
+                ++p;
+                added = 1;
+            }
+        }
+        if (!added) break;
+        lp_t lp;
+        lp_build_cuts(&lp, n, rowptr, col, gamma, p, chk, Vs);
+        free(x); free(z); free(y);
+        x = malloc(sizeof(double) * (n + p));
+        z = malloc(sizeof(double) * (n + p));
+        y = malloc(sizeof(double) * (p + 1));
+        int its = 0;
+        int rc = ipm_solve(&lp, o, x, y, z, &its);
+        s.malp_iters++;
+        s.ipm_iters += its;
+        if (p > s.p_max) s.p_max = p;
+        s.p_final = p;
+        double cost = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double ui = gamma[i] >= 0.0 ? x[i] : 1.0 - x[i];
+            if (o->box_clamp) ui = ui < 0.0 ? 0.0 : (ui > 1.0 ? 1.0 : ui);
+            u[i] = ui;
+            cost += gamma[i] * ui;
+        }
+        if (trace_obj && k < trace_cap) {
+            trace_obj[k] = cost;
+            trace_p[k] = p;
+            trace_ipm[k] = its;
+        }
+        lp_free(&lp);
+        if (rc != 0) { s.status = rc; break; }
+        if (cost < cost_prev - o->tau_cost * (1.0 + fabs(cost_prev - gneg))) { s.status = -5; break; }
+        cost_prev = cost;
+    }
+    if (k == o->malp_max && s.status == 0) s.status = -3;
+    double fr = 0.0, g = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double a = u[i] < 1.0 - u[i] ? u[i] : 1.0 - u[i];
+        if (a > fr) fr = a;
+        g += gamma[i] * u[i];
+        if (fabs(u[i] - 0.5) <= o->tau_int) xhat[i] = gamma[i] >= 0.0 ? 0 : 1;
+        else xhat[i] = u[i] > 0.5;
+    }
+    int syn = 0;
+    for (int j = 0; j < m; ++j) {
+        int par = 0;
+        for (int t = rowptr[j]; t < rowptr[j + 1]; ++t) par ^= xhat[col[t]];
+        syn |= par;
+    }
+    int integral = fr <= o->tau_int;
+    if (s.status < 0) *flag = s.status;
+    else if (integral && !syn) *flag = 1;
+    else if (integral) *flag = -4;
+    else *flag = 0;
+    if (obj) *obj = g;
+    if (u_out) memcpy(u_out, u, sizeof(double) * n);
+    if (st) *st = s;
+    if (cuts_out)
+        for (int r = 0; r < p && r < cuts_cap; ++r) { cuts_out[2 * r] = chk[r]; cuts_out[2 * r + 1] = (int)Vs[r]; }
+    free(chk); free(Vs); free(u); free(nb); free(x); free(z); free(y);
+    return p;
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -268,3 +268,35 @@ def mts_inc(code, hascut, w):
     p = _L().orc_mts_inc(C.c_int(code.m), C.c_int(code.n), _p(_i32(code.rowptr)), _p(_i32(code.col)),
                          _p(hascut), _p(w), _p(pair), _p(order), C.byref(calls))
     return pair, order[:p], int(calls.value)
+
+
+@dataclass
+class AlpResult(DecodeResult):
+    cuts: np.ndarray | None = None     # [ncuts, 2]: check, V of every cut of the last LP
+
+
+def alp_decode(code, gamma, opts: OracleOpts | None = None) -> AlpResult:
+    """ALP decoding (Algorithm 1): every violated parity inequality is added and none removed.
+    trace_p / trace_obj / trace_ipm: cuts, cost and IPM iterations of each LP."""
+    opts = opts or OracleOpts()
+    gamma = _f64(gamma)
+    m, n = code.m, code.n
+    u = np.zeros(n)
+    xh = np.zeros(n, dtype=np.uint8)
+    flag = C.c_int(0)
+    obj = C.c_double(0)
+    st = _Stats()
+    o = opts.c()
+    cap = opts.malp_max
+    to = np.zeros(cap)
+    tp = np.zeros(cap, dtype=np.int32)
+    ti = np.zeros(cap, dtype=np.int32)
+    ccap = 64 * m + 64
+    cuts = np.zeros((ccap, 2), dtype=np.int32)
+    nc = _L().orc_alp_decode(C.c_int(m), C.c_int(n), _p(_i32(code.rowptr)), _p(_i32(code.col)), _p(gamma),
+                             C.byref(o), _p(u), _p(xh), C.byref(flag), C.byref(obj), C.byref(st),
+                             _p(to), _p(tp), _p(ti), C.c_int(cap), _p(cuts), C.c_int(ccap))
+    k = st.malp_iters
+    return AlpResult(u, xh, int(flag.value), float(obj.value), st.malp_iters, st.ipm_iters, st.p_max,
+                     st.p_final, st.status, None, to[:k].copy(), tp[:k].copy(), ti[:k].copy(),
+                     cuts[:min(nc, ccap)].copy())

@@ -826,3 +826,49 @@ def test_mts_inc_closed_forms(orc):
     pair, order, _ = orc.mts_inc(code, one, w)
     cand = list(code.row(5)) + [code.n + 5]
     assert pair[5] == max(cand, key=lambda c: (np.float32(w[c]), -c))
+
+
+# ---------------------------------------------------------------- ALP decoding (Algorithm 1)
+@pytest.mark.parametrize("snr", [1.0, 1.5, 2.5])
+def test_alp_equals_lp_decoding_and_malp(orc, snr):
+    """Theorem 2c for ALP: its last LP solution is the LP-decoding optimum, the same as MALP-A's
+    and HiGHS' over every odd-set inequality. Theorem 1: an iteration adds at most one cut per
+    check (the new cuts of each LP have distinct checks). Theorem 2b: costs increase. Every cut
+    kept is satisfied at the output."""
+    code = regular_code(96)
+    n_frac = 0
+    for gamma in _frames(code, [snr], 8, 131):
+        a = orc.alp_decode(code, gamma)
+        r = orc.decode(code, gamma)
+        fun, _ = refs.feldman_lp(code, gamma)
+        scale = 1.0 + abs(fun - gamma[gamma < 0].sum())
+        assert a.status == 0 and a.flag == r.flag
+        assert abs(a.objective - fun) <= 1e-6 * scale and abs(a.objective - r.objective) <= 1e-6 * scale
+        assert np.array_equal(a.xhat, r.xhat)
+        assert a.malp_iters <= code.n
+        assert np.all(np.diff(a.trace_obj) > 0)
+        bounds = np.concatenate([[0], a.trace_p])
+        for k in range(a.malp_iters):
+            new = a.cuts[bounds[k]:bounds[k + 1], 0]
+            assert 1 <= len(new) <= code.m and np.all(np.diff(new) > 0)
+        for j, V in a.cuts:
+            arow, b = refs.cut_row_u(code, int(j), int(V))
+            assert arow @ a.u <= b + 1e-6
+        n_frac += a.flag == 0
+    if snr == 1.0:
+        assert n_frac >= 2
+
+
+def test_alp_keeps_every_cut_and_solves_larger_lps(orc):
+    """ALP never removes a cut, so its LPs grow monotonically, and its largest LP is at least
+    as large as MALP-A's last one on the same frame (MALP keeps one cut per check)."""
+    code = regular_code(240)
+    for gamma in _frames(code, [1.5, 2.0], 6, 132):
+        a = orc.alp_decode(code, gamma)
+        r = orc.decode(code, gamma)
+        if a.malp_iters == 0:
+            assert r.malp_iters == 0
+            continue
+        assert np.all(np.diff(a.trace_p) > 0)
+        assert a.p_max == a.trace_p[-1] >= r.p_final
+        assert len({(int(j), int(V)) for j, V in a.cuts}) == len(a.cuts)
