@@ -334,7 +334,8 @@ def precond_study(seed=606):
     ctx.set_option("PRECISION", 1)
     C = Code.from_synth(ctx, code)
     names = {4: "CG (no preconditioner)", 0: "slack columns (diagonal)", 1: "Algorithm 7 (column-wise)",
-             2: "Algorithm 8 (row-wise, diagonal expansion)", 3: "Algorithm 8 (row-wise, triangular expansion)"}
+             2: "Algorithm 8 (row-wise, diagonal expansion)", 3: "Algorithm 8 (row-wise, triangular expansion)",
+             5: "Algorithm 6 (incremental)"}
     steps = (5, 10, 20, 40, 80, 120, 160, 200)
     systems = []
     for label, snr, want in (("integral, 1.5 dB", 1.5, 1), ("fractional, 1.0 dB", 1.0, 0)):
@@ -387,7 +388,7 @@ def precond_study(seed=606):
             sysrec = {"system": label, "frame": int(f), "malp_iterations": int(malp[f]), "ipm_iteration": it,
                       "rows": p, "columns": n + p, "duality_gap": float(xa @ za), "kappa": float(ev[-1] / ev[0]),
                       "residual2": {}}
-            for pc in (4, 0, 1, 2, 3):
+            for pc in (4, 0, 1, 2, 3, 5):
                 ctx.set_option("PRECOND", pc)
                 ctx.set_option("REF_MAX", 0)
                 ctx.set_option("PCG_TOL", 1e-30)
@@ -406,6 +407,88 @@ def precond_study(seed=606):
     ctx.close()
     return {"precond_study": {"code": "(3,6)-regular n=2000, 4-cycle free", "lp": "6th MALP-A iteration",
                               "metric": "||w - Q y||^2 / ||w||^2 after k FP64 PCG iterations", "systems": systems}}
+
+
+PRECOND_NAMES = {1: "Algorithm 7 (column-wise)", 2: "Algorithm 8 (row-wise, diagonal expansion)",
+                 3: "Algorithm 8 (row-wise, triangular expansion)", 5: "Algorithm 6 (incremental)",
+                 0: "slack columns (diagonal)", 4: "CG (no preconditioner)"}
+
+
+def precond_compare(dev, stream, name="c2", preconds=(1, 2, 3, 5, 0, 4), method_only=False):
+    """One launch of a whole workload per preconditioner: the share of Newton systems that PCG
+    solves within the automatic cap (the rest go to the dense fallback), PCG iterations per
+    PCG-solved system, search cost and launch time; with method_only, no dense fallback (FP64
+    PCG, cap 2000) and the PCG iterations per system. Parity against the stored oracle
+    results in every row."""
+    import torch
+    from paper_0902_0657_amd import Code, Context, stats_table
+    code, G = workload(name)
+    g = torch.as_tensor(G, device=dev)
+    rows = []
+    for pc in preconds:
+        opts = {"PRECOND": pc, "PRECISION": 1}
+        if method_only:
+            opts.update({"DIRECT_FALLBACK": 0, "PCG_MAXIT": 2000})
+        ctx = Context(0, **opts)
+        C = Code.from_synth(ctx, code)
+        out, ms, _ = run_leg(ctx, C, g, G.shape[0], dev, stream, 1, 0, f"precond {pc}")
+        st = stats_table(out["stats"])
+        flags, xhat, objs = out["flag"].cpu().numpy(), out["xhat"].cpu().numpy(), out["obj"].cpu().numpy()
+        newton = int(st["ipm_iters"].sum())
+        dense = int(st["direct_solves"].sum())
+        rows.append({"precond": pc, "name": PRECOND_NAMES[pc], "launch_ms": float(ms.mean()),
+                     "newton_systems": newton, "solved_by_pcg": 1.0 - dense / max(1, newton),
+                     "pcg_iterations": int(st["pcg_iters"].sum()),
+                     "pcg_per_newton": float(st["pcg_iters"].sum()) / max(1, newton),
+                     "search_us_per_ipm_iteration": float(st["ticks_mts"].sum()) / 100.0 / max(1, newton),
+                     "pcg_us_per_iteration": float(st["ticks_pcg"].sum()) / 100.0 / max(1, int(st["pcg_iters"].sum())),
+                     "parity_vs_oracle": golden_parity(name, code, G, flags, xhat, objs)})
+        log(f"precond {pc}: {ms.mean():.0f} ms, {rows[-1]['solved_by_pcg']:.3f} by PCG")
+        ctx.close()
+    return {"workload": name, "method_only": method_only, "rows": rows}
+
+
+def alp_study(dev, stream, name="c2"):
+    """Sec. III-D on a whole workload: LPs solved and the size of the largest LP for ALP
+    (Algorithm 1), MALP-A and MALP-B, split by integral and fractional output (mean and the
+    95% one-sided upper bound), and the size of MALP's largest LP relative to ALP's."""
+    import torch
+    from paper_0902_0657_amd import Code, Context, stats_table
+    code, G = workload(name)
+    g = torch.as_tensor(G, device=dev)
+    res = {}
+    for label, mode in (("MALP-A", 0), ("MALP-B", 1)):
+        ctx = Context(0, MALP_MODE=mode)
+        C = Code.from_synth(ctx, code)
+        out, ms, _ = run_leg(ctx, C, g, G.shape[0], dev, stream, 1, 0, label)
+        st = stats_table(out["stats"])
+        res[label] = {"flags": out["flag"].cpu().numpy(), "lps": st["malp_iters"], "p": st["p_max"],
+                      "ms": float(ms.mean())}
+        ctx.close()
+    ctx = Context(0)
+    C = Code.from_synth(ctx, code)
+    t0 = time.perf_counter()
+    out = ctx.alp_decode_batch(C, G.astype(np.float64))
+    st = stats_table(out["stats"])
+    res["ALP"] = {"flags": out["flag"], "lps": st["malp_iters"], "p": st["p_max"],
+                  "ms": (time.perf_counter() - t0) * 1e3}
+    gold = json.load(open(os.path.join(GOLDEN, GOLDEN_FILES[name])))["frames"]
+    integral = np.array([gold[str(f)]["flag"] == 1 for f in range(G.shape[0])])
+    summary = {}
+    for label, r in res.items():
+        rec = {"ms": r["ms"], "flags": {str(k): int(v) for k, v in zip(*np.unique(r["flags"], return_counts=True))},
+               "matches_oracle_flags": int(sum(int(r["flags"][f]) == gold[str(f)]["flag"] for f in range(G.shape[0])))}
+        for part, sel in (("integral", integral), ("fractional", ~integral)):
+            lps, p = r["lps"][sel].astype(float), r["p"][sel].astype(float)
+            rec[part] = {"frames": int(sel.sum()), "lps_mean": float(lps.mean()), "lps_p95": float(np.percentile(lps, 95)),
+                         "largest_lp_mean": float(p.mean())}
+        summary[label] = rec
+    for label in ("MALP-A", "MALP-B"):
+        for part, sel in (("integral", integral), ("fractional", ~integral)):
+            summary[label][part]["largest_lp_vs_alp"] = float(
+                np.mean(res[label]["p"][sel].astype(float) / np.maximum(1, res["ALP"]["p"][sel])))
+    ctx.close()
+    return {"workload": name, "study": "Sec. III-D", "modes": summary}
 
 
 def sources_digest():
@@ -538,6 +621,12 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precond-study", action="store_true",
                     help="print the preconditioner comparison of Sec. VI-B (n=2000 code) instead of the benchmark")
+    ap.add_argument("--precond-compare", default="",
+                    help="print the preconditioners' Newton-system shares on a whole workload (c2 or c3) instead "
+                         "of the benchmark; with --method-only, without the dense fallback")
+    ap.add_argument("--method-only", action="store_true")
+    ap.add_argument("--alp-study", action="store_true",
+                    help="print ALP / MALP-A / MALP-B LP counts and sizes on the n=1024 batch (Sec. III-D)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (one GPU's share of the batch); "
@@ -547,6 +636,15 @@ def main():
 
     if args.precond_study:
         print(json.dumps(precond_study()))
+        return
+    if args.precond_compare or args.alp_study:
+        import torch
+        dev = torch.device("cuda:0")
+        stream = torch.cuda.current_stream(dev)
+        if args.precond_compare:
+            print(json.dumps(precond_compare(dev, stream, args.precond_compare, method_only=args.method_only)))
+        if args.alp_study:
+            print(json.dumps(alp_study(dev, stream)))
         return
     import torch
     from paper_0902_0657_amd import Code, Context, _lib

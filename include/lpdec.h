@@ -55,6 +55,8 @@ typedef int32_t lpdec_status;
 #define LPDEC_FLAG_INCONSISTENT (-4)/* integral output that violates a check */
 #define LPDEC_FLAG_COST_DECREASE (-5)/* an LP's cost fell below the previous LP's beyond TAU_COST
                                         (impossible in exact arithmetic, Theorem 2b) */
+#define LPDEC_FLAG_ALP_CAPACITY (-6) /* ALP only: the LP outgrew the list encoding (a variable in
+                                        more than 16 cuts, or more than 16383 - n cuts) */
 
 typedef struct lpdec_ctx lpdec_ctx;
 typedef struct lpdec_code lpdec_code;
@@ -120,7 +122,9 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  3 = Algorithm 8 with triangular expansion (the unmatched rows by the
  *                  column-wise greedy over the columns of unmatched rows only), 0 = the slack
  *                  columns as preconditioning set (a diagonal preconditioner), 4 = no
- *                  preconditioner (plain CG on A D^2 A^T in FP64, the baseline of Sec. VI-B)
+ *                  preconditioner (plain CG on A D^2 A^T in FP64, the baseline of Sec. VI-B),
+ *                  5 = from Algorithm 6 (incremental greedy search with the Triangulation Step
+ *                  of Algorithm 5; O(q^2) work per search, blocks of columns tested at once)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
  *                  perturbs the complementarity equation by at most XI_TOL * mu (0.03)
  *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
@@ -234,6 +238,22 @@ lpdec_status lpdec_decode_batch_noalloc(lpdec_ctx *ctx, const lpdec_code *code, 
                                         int32_t *flag_dev, double *obj_dev, lpdec_stats *stats_dev,
                                         double *u_dev, void *stream);
 
+/* ALP decoding (Algorithm 1, Sec. II-C) of a batch, for comparison with MALP (Sec. III-D):
+ * every violated parity inequality found by Algorithm 2 at the last solution is added and no
+ * cut is ever removed, so a check can hold several cuts and an LP has one row per cut. Host
+ * pointers, synchronous: gamma double[nframes*n]; outputs xhat uint8[nframes*n], flag
+ * int32[nframes] (as lpdec_decode; LPDEC_FLAG_ALP_CAPACITY when the LP outgrows the list
+ * encoding), objective double[nframes] (nullable), stats lpdec_stats[nframes] (nullable;
+ * malp_iters = LPs solved, p_max = cuts in the largest LP), u double[nframes*n] (nullable).
+ * The iterations run in lockstep over the frames still decoding: each runs Algorithm 2 on
+ * every check of every such frame in one launch, appends the new cuts on the host, and solves
+ * every frame's LP in one interior-point launch in which each frame has its own matrix (a copy
+ * of its cut's check row per cut). Uses the context's options (TAU_VIOL, IPM settings,
+ * PRECOND, PRECISION, ...). */
+lpdec_status lpdec_alp_decode_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                    const double *gamma, uint8_t *xhat, int32_t *flag, double *objective,
+                                    lpdec_stats *stats, double *u);
+
 /* ---- steps of the hot path, one frame per workgroup, device pointers, synchronous ----- */
 /* Algorithm 2 on every check at the points u_dev (double[nframes*n]):
  * vmask_dev uint32[nframes*m] = V of the check's minimising odd set, viol_dev uint8[nframes*m]
@@ -244,14 +264,17 @@ lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int3
 
 /* The triangular-set search of the context's PRECOND on the LP whose rows are the checks
  * with hascut_dev[f*m+j] != 0: Algorithm 7 (PRECOND 0, 1 or 4; columns ordered by weight
- * descending, then index ascending) or Algorithm 8 with diagonal (PRECOND 2) or triangular
+ * descending, then index ascending), Algorithm 8 with diagonal (PRECOND 2) or triangular
  * (PRECOND 3) expansion (the lowest-indexed row of degree 1 first, columns removed by weight
- * ascending, then index ascending; the triangular expansion then uses Algorithm 7's order). Column weights w_dev float[nframes*(n+m)] (standard column i at i, slack of
+ * ascending, then index ascending; the triangular expansion then uses Algorithm 7's order), or
+ * Algorithm 6 (PRECOND 5; columns tried by weight descending, then index ascending; the
+ * Triangulation Step peels in rounds, a column proposed by several rows of degree 1 going to the
+ * lowest-indexed one). Column weights w_dev float[nframes*(n+m)] (standard column i at i, slack of
  * check j at n+j). Outputs: pair_dev int32[nframes*m]
  * = column matched to row j (-1 for checks without a cut); lev_b_dev / lev_f_dev
  * int32[nframes*m] = dependency level of row j in the back- and forward-substitution of the
  * preconditioner solve (-1 without a cut); rounds_dev int32[nframes] (nullable) = greedy
- * steps taken (one per LP row, p). */
+ * steps taken (one per LP row, p), or Triangulation Steps run (PRECOND 5). */
 lpdec_status lpdec_mts_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
                              const uint8_t *hascut_dev, const float *w_dev, int32_t *pair_dev,
                              int32_t *lev_b_dev, int32_t *lev_f_dev, int32_t *rounds_dev);

@@ -94,6 +94,24 @@ class Context:
                                         C.byref(st), u.ctypes.data_as(C.c_void_p)))
         return xhat, int(flag.value), float(obj.value), {f: getattr(st, f) for f in STATS_FIELDS}, u
 
+    def alp_decode_batch(self, code: "Code", gamma):
+        """ALP decoding (lpdec_alp_decode_batch) of frames from host memory: gamma [nframes, n].
+        Returns a dict of numpy arrays: xhat, flag, obj, u and stats (lpdec_stats rows)."""
+        g = np.ascontiguousarray(gamma, dtype=np.float64)
+        assert g.ndim == 2 and g.shape[1] == code.n
+        nf = g.shape[0]
+        xhat = np.zeros((nf, code.n), dtype=np.uint8)
+        flag = np.zeros(nf, dtype=np.int32)
+        obj = np.zeros(nf, dtype=np.float64)
+        u = np.zeros((nf, code.n), dtype=np.float64)
+        st = (Stats * max(nf, 1))()
+        self._check(self.L.lpdec_alp_decode_batch(self.h, code.h, nf, g.ctypes.data_as(C.c_void_p),
+                                                  xhat.ctypes.data_as(C.c_void_p), flag.ctypes.data_as(C.c_void_p),
+                                                  obj.ctypes.data_as(C.c_void_p), C.cast(st, C.c_void_p),
+                                                  u.ctypes.data_as(C.c_void_p)))
+        stats = np.frombuffer(bytes(st), dtype=np.int32).reshape(max(nf, 1), STATS_WORDS)[:nf].copy()
+        return {"xhat": xhat, "flag": flag, "obj": obj, "u": u, "stats": stats}
+
     @staticmethod
     def batch_outputs(code: "Code", nf, device, want_u=False, want_stats=True):
         """Output tensors of decode_batch for nf frames (allocated, not filled)."""

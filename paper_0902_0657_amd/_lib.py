@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblpdec.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT, FLAG_COST_DECREASE = -1, -2, -3, -4, -5
+FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT, FLAG_COST_DECREASE, FLAG_ALP_CAPACITY = \
+    -1, -2, -3, -4, -5, -6
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",
@@ -43,6 +44,7 @@ _SIGS = {
     "lpdec_code_destroy": (_I, [_P]),
     "lpdec_decode": (_I, [_P, _P, _P, _P, C.POINTER(_I), C.POINTER(_D), C.POINTER(Stats), _P]),
     "lpdec_decode_batch": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P]),
+    "lpdec_alp_decode_batch": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P]),
     "lpdec_decode_batch_noalloc": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P]),
     "lpdec_decode_batch_trace": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _I]),
     "lpdec_cut_search_batch": (_I, [_P, _P, _I, _P, _P, _P, _P]),

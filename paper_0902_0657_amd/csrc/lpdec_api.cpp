@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -289,7 +290,7 @@ extern "C" lpdec_status lpdec_set_option(lpdec_ctx *ctx, int32_t key, double v)
         if (!(v == 0 || (ipos(64) && v <= 256 && ((int)v % 64) == 0))) break;
         ctx->block = (int)v;
         return LPDEC_OK;
-    case LPDEC_OPT_PRECOND: if (!(ipos(0) && v <= 4)) break; o.precond = (int)v; return LPDEC_OK;
+    case LPDEC_OPT_PRECOND: if (!(ipos(0) && v <= 5)) break; o.precond = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_STREAMS: if (!ipos(1) || v > 32) break; ctx->server_streams = (int)v; return LPDEC_OK;
     case LPDEC_OPT_SERVER_MODE: if (v != 0 && v != 1) break; ctx->server_mode = (int)v; return LPDEC_OK;
     case LPDEC_OPT_DISPATCH_ORDER: if (v != 0 && v != 1) break; ctx->dispatch_order = (int)v; return LPDEC_OK;
@@ -512,6 +513,273 @@ static lpdec_status run_sync(lpdec_ctx *ctx, const lpdec_code *code, Args &a, in
     if (st) return st;
     hipError_t e = hipDeviceSynchronize();
     return e == hipSuccess ? LPDEC_OK : hipfail(ctx, e, "kernel");
+}
+
+
+// ------------------------------------------------------------------------------ ALP
+namespace {
+
+// A device buffer freed with its owner (host code of the ALP entry point only).
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t get(size_t bytes)
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        return hipMalloc(&p, bytes ? bytes : 1);
+    }
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+struct AlpFrame {
+    std::vector<int> chk;        // check of every cut, in the order the cuts were added
+    std::vector<uint32_t> V;     // odd set of every cut (bit k = k-th variable of the check)
+    std::vector<double> u;       // the last LP solution (hard decisions before the first)
+    double gneg = 0.0, cost_prev = 0.0;
+    int status = 0;
+    bool done = false;
+    lpdec_stats st{};
+};
+
+}  // namespace
+
+extern "C" lpdec_status lpdec_alp_decode_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,
+                                               const double *gamma, uint8_t *xhat, int32_t *flag,
+                                               double *objective, lpdec_stats *stats, double *u_out)
+{
+    lpdec_status st = check_common(ctx, code, nframes);
+    if (st) return st;
+    if (nframes == 0) return LPDEC_OK;
+    if (!gamma || !xhat || !flag) return fail(ctx, LPDEC_EINVAL, "null gamma/xhat/flag");
+    const int m = code->m, n = code->n, nf = nframes;
+    const lpdec::Opts &o = ctx->opts;
+    const int pt64 = precision_for(ctx, 1);
+    std::vector<AlpFrame> F(nf);
+    for (int f = 0; f < nf; ++f) {
+        F[f].u.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const double g = gamma[(size_t)f * n + i];
+            F[f].u[i] = g >= 0.0 ? 0.0 : 1.0;
+            if (g < 0.0) F[f].gneg += g;
+        }
+        F[f].cost_prev = F[f].gneg;
+    }
+    DevBuf d_gamma, d_u, d_vm, d_viol, d_lhs;
+    hipError_t e = d_gamma.get(8 * (size_t)nf * n);
+    if (e == hipSuccess) e = d_u.get(8 * (size_t)nf * n);
+    if (e == hipSuccess) e = d_vm.get(4 * (size_t)nf * m);
+    if (e == hipSuccess) e = d_viol.get((size_t)nf * m);
+    if (e == hipSuccess) e = d_lhs.get(8 * (size_t)nf * m);
+    if (e != hipSuccess) return hipfail(ctx, e, "ALP buffers");
+    std::vector<double> hu((size_t)nf * n), hg((size_t)nf * n);
+    std::vector<uint32_t> hvm((size_t)nf * m);
+    std::vector<uint8_t> hviol((size_t)nf * m);
+    std::vector<int> act;
+    for (int k = 0; k < o.malp_max; ++k) {
+        act.clear();
+        for (int f = 0; f < nf; ++f)
+            if (!F[f].done) act.push_back(f);
+        if (act.empty()) break;
+        const int na = (int)act.size();
+        // Algorithm 2 on every check at the last solution of every active frame
+        for (int a = 0; a < na; ++a) std::memcpy(&hu[(size_t)a * n], F[act[a]].u.data(), 8 * (size_t)n);
+        e = hipMemcpy(d_u.p, hu.data(), 8 * (size_t)na * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(ctx, e, "ALP upload");
+        Args ac{};
+        ac.nframes = na; ac.mode = lpdec::MODE_CUTS;
+        ac.vec_in = d_u.as<double>(); ac.u32_out = d_vm.as<uint32_t>(); ac.u8_out = d_viol.as<uint8_t>();
+        ac.vec_out = d_lhs.as<double>();
+        st = run_sync(ctx, code, ac, 1);
+        if (st) return st;
+        e = hipMemcpy(hvm.data(), d_vm.p, 4 * (size_t)na * m, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(hviol.data(), d_viol.p, (size_t)na * m, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hipfail(ctx, e, "ALP cut search");
+        // every violated inequality joins its frame's LP; no cut is ever removed
+        std::vector<int> lp;   // frames with new cuts
+        for (int a = 0; a < na; ++a) {
+            AlpFrame &R = F[act[a]];
+            bool added = false;
+            for (int j = 0; j < m; ++j)
+                if (hviol[(size_t)a * m + j]) {
+                    R.chk.push_back(j);
+                    R.V.push_back(hvm[(size_t)a * m + j]);
+                    added = true;
+                }
+            if (added) lp.push_back(act[a]);
+            else R.done = true;
+        }
+        if (lp.empty()) break;
+        // a frame whose LP no longer fits the list encoding (a variable in more than 16 cuts,
+        // or more than 16383 - n cuts) ends with LPDEC_FLAG_ALP_CAPACITY
+        {
+            std::vector<int> keep, cnt(n);
+            for (int f : lp) {
+                const AlpFrame &R = F[f];
+                std::fill(cnt.begin(), cnt.end(), 0);
+                int dv = 0;
+                for (int j : R.chk)
+                    for (int t = code->rowptr[j]; t < code->rowptr[j + 1]; ++t) dv = std::max(dv, ++cnt[code->col[t]]);
+                if (dv > 16 || (int)R.chk.size() + n > 16383) {
+                    F[f].status = LPDEC_FLAG_ALP_CAPACITY;
+                    F[f].done = true;
+                } else {
+                    keep.push_back(f);
+                }
+            }
+            lp.swap(keep);
+        }
+        if (lp.empty()) continue;
+        // one matrix per frame: row r is the row of the check of cut r; empty rows pad every
+        // frame to the largest cut count of the launch (they carry no cut, so the LP ignores them)
+        const int nl = (int)lp.size();
+        int M = 0;
+        for (int f : lp) M = std::max(M, (int)F[f].chk.size());
+        std::vector<std::vector<int>> rp(nl), cl(nl), cp(nl), vl(nl);
+        int dvmax = 1;
+        size_t words = 0;
+        for (int b = 0; b < nl; ++b) {
+            const AlpFrame &R = F[lp[b]];
+            auto &rowp = rp[b], &colv = cl[b], &colp = cp[b], &vlst = vl[b];
+            rowp.assign(M + 1, 0);
+            for (int r = 0; r < (int)R.chk.size(); ++r) {
+                const int j = R.chk[r];
+                for (int t = code->rowptr[j]; t < code->rowptr[j + 1]; ++t) colv.push_back(code->col[t]);
+                rowp[r + 1] = (int)colv.size();
+            }
+            for (int r = (int)R.chk.size(); r < M; ++r) rowp[r + 1] = (int)colv.size();
+            const int E = (int)colv.size();
+            colp.assign(n + 1, 0);
+            for (int t = 0; t < E; ++t) colp[colv[t] + 1]++;
+            for (int i = 0; i < n; ++i) {
+                dvmax = std::max(dvmax, colp[i + 1]);
+                colp[i + 1] += colp[i];
+            }
+            vlst.assign(E, 0);
+            std::vector<int> fill(colp.begin(), colp.end() - 1);
+            for (int r = 0; r < M; ++r)
+                for (int t = rowp[r]; t < rowp[r + 1]; ++t) vlst[fill[colv[t]]++] = (r << 5) | (t - rowp[r]);
+            words += (size_t)(M + 1) + E + (n + 1) + E;
+        }
+        std::vector<int> hcsr(words);
+        std::vector<lpdec::CodeView> views(nl);
+        std::vector<uint32_t> hmask((size_t)nl * M, 0u);
+        DevBuf d_csr, d_views, d_mask, d_g, d_x, d_z, d_y, d_its, d_status, d_stats;
+        e = d_csr.get(4 * words);
+        if (e == hipSuccess) e = d_views.get(sizeof(lpdec::CodeView) * nl);
+        if (e == hipSuccess) e = d_mask.get(4 * (size_t)nl * M);
+        if (e == hipSuccess) e = d_g.get(8 * (size_t)nl * n);
+        if (e == hipSuccess) e = d_x.get(8 * (size_t)nl * (n + M));
+        if (e == hipSuccess) e = d_z.get(8 * (size_t)nl * (n + M));
+        if (e == hipSuccess) e = d_y.get(8 * (size_t)nl * M);
+        if (e == hipSuccess) e = d_its.get(4 * (size_t)nl);
+        if (e == hipSuccess) e = d_status.get(4 * (size_t)nl);
+        if (e == hipSuccess) e = d_stats.get(sizeof(lpdec_stats) * nl);
+        if (e != hipSuccess) return hipfail(ctx, e, "ALP LP buffers");
+        size_t w = 0;
+        for (int b = 0; b < nl; ++b) {
+            const AlpFrame &R = F[lp[b]];
+            const int E = (int)cl[b].size();
+            lpdec::CodeView &v = views[b];
+            v.m = M; v.n = n; v.E = E; v.dcmax = code->dcmax; v.dvmax = dvmax;
+            int *base = d_csr.as<int>() + w;
+            std::memcpy(&hcsr[w], rp[b].data(), 4 * (size_t)(M + 1)); v.rowptr = base; w += M + 1; base += M + 1;
+            std::memcpy(&hcsr[w], cl[b].data(), 4 * (size_t)E); v.col = base; w += E; base += E;
+            std::memcpy(&hcsr[w], cp[b].data(), 4 * (size_t)(n + 1)); v.colptr = base; w += n + 1; base += n + 1;
+            std::memcpy(&hcsr[w], vl[b].data(), 4 * (size_t)E); v.vlist = base; w += E;
+            for (int r = 0; r < (int)R.V.size(); ++r) hmask[(size_t)b * M + r] = R.V[r];
+            std::memcpy(&hg[(size_t)b * n], gamma + (size_t)lp[b] * n, 8 * (size_t)n);
+        }
+        e = hipMemcpy(d_csr.p, hcsr.data(), 4 * words, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_views.p, views.data(), sizeof(lpdec::CodeView) * nl, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_mask.p, hmask.data(), 4 * (size_t)nl * M, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_g.p, hg.data(), 8 * (size_t)nl * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(ctx, e, "ALP LP upload");
+        // the launch is sized for the padded matrices (M rows, column degree dvmax)
+        lpdec_code shape;
+        shape.m = M; shape.n = n; shape.E = 0; shape.dcmax = code->dcmax; shape.dvmax = dvmax;
+        Args ai{};
+        ai.nframes = nl; ai.mode = lpdec::MODE_IPM; ai.codes = d_views.as<lpdec::CodeView>();
+        ai.gamma = d_g.p; ai.gamma_f64 = 1; ai.vmask_in = d_mask.as<uint32_t>();
+        ai.x_out = d_x.as<double>(); ai.z_out = d_z.as<double>(); ai.vec_out = d_y.as<double>();
+        ai.i_out = d_its.as<int32_t>(); ai.i_out2 = d_status.as<int32_t>(); ai.stats = d_stats.as<lpdec_stats>();
+        st = run_sync(ctx, &shape, ai, pt64);
+        if (st) return st;
+        std::vector<double> hx((size_t)nl * (n + M));
+        std::vector<int32_t> hits(nl), hst(nl);
+        std::vector<lpdec_stats> hs(nl);
+        e = hipMemcpy(hx.data(), d_x.p, 8 * hx.size(), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(hits.data(), d_its.p, 4 * (size_t)nl, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(hst.data(), d_status.p, 4 * (size_t)nl, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(hs.data(), d_stats.p, sizeof(lpdec_stats) * nl, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hipfail(ctx, e, "ALP LP results");
+        for (int b = 0; b < nl; ++b) {
+            AlpFrame &R = F[lp[b]];
+            const double *g = gamma + (size_t)lp[b] * n;
+            const double *x = &hx[(size_t)b * (n + M)];
+            R.st.malp_iters++;
+            R.st.ipm_iters += hits[b];
+            R.st.pcg_iters += hs[b].pcg_iters;
+            R.st.ref_rounds += hs[b].ref_rounds;
+            R.st.mts_rounds += hs[b].mts_rounds;
+            R.st.escalations += hs[b].escalations;
+            R.st.direct_solves += hs[b].direct_solves;
+            R.st.max_levels = std::max(R.st.max_levels, hs[b].max_levels);
+            R.st.pcg_rows += hs[b].pcg_rows;
+            R.st.ipm_cols += hs[b].ipm_cols;
+            R.st.ticks_mts += hs[b].ticks_mts;
+            R.st.ticks_solve += hs[b].ticks_solve;
+            R.st.ticks_pcg += hs[b].ticks_pcg;
+            R.st.ticks_dense += hs[b].ticks_dense;
+            R.st.dense_cube += hs[b].dense_cube;
+            R.st.p_max = std::max(R.st.p_max, (int)R.chk.size());
+            if (hst[b] < 0) { R.status = hst[b]; R.done = true; continue; }
+            // u^k on the box (Theorem 2a), then the cost check (Theorem 2b), as in MALP
+            double cost = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double ui = std::min(1.0, std::max(0.0, g[i] >= 0.0 ? x[i] : 1.0 - x[i]));
+                R.u[i] = ui;
+                cost += g[i] * ui;
+            }
+            if (cost < R.cost_prev - o.tau_cost * (1.0 + std::fabs(R.cost_prev - R.gneg))) {
+                R.status = LPDEC_FLAG_COST_DECREASE;
+                R.done = true;
+                continue;
+            }
+            R.cost_prev = cost;
+        }
+    }
+    // output: integrality, decisions, syndrome, certificate flag, objective
+    for (int f = 0; f < nf; ++f) {
+        AlpFrame &R = F[f];
+        if (!R.done && R.status == 0) R.status = LPDEC_FLAG_MALP_CAP;
+        const double *g = gamma + (size_t)f * n;
+        uint8_t *xh = xhat + (size_t)f * n;
+        double fr = 0.0, ob = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double ui = R.u[i];
+            fr = std::max(fr, std::min(ui, 1.0 - ui));
+            ob += g[i] * ui;
+            xh[i] = std::fabs(ui - 0.5) <= o.tau_int ? (g[i] >= 0.0 ? 0 : 1) : (ui > 0.5 ? 1 : 0);
+            if (u_out) u_out[(size_t)f * n + i] = ui;
+        }
+        int syn = 0;
+        for (int j = 0; j < m; ++j) {
+            int par = 0;
+            for (int t = code->rowptr[j]; t < code->rowptr[j + 1]; ++t) par ^= xh[code->col[t]];
+            syn |= par;
+        }
+        int fl;
+        if (R.status < 0) fl = R.status;
+        else if (fr <= o.tau_int && !syn) fl = 1;
+        else if (fr <= o.tau_int) fl = LPDEC_FLAG_INCONSISTENT;
+        else fl = 0;
+        flag[f] = fl;
+        if (objective) objective[f] = ob;
+        R.st.status = R.status < 0 ? R.status : 0;
+        if (stats) stats[f] = R.st;
+    }
+    return LPDEC_OK;
 }
 
 extern "C" lpdec_status lpdec_cut_search_batch(lpdec_ctx *ctx, const lpdec_code *code, int32_t nframes,

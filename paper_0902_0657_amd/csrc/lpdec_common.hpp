@@ -167,6 +167,7 @@ enum Mode : int {
 // Kernel arguments (one struct, passed by value).
 struct Args {
     CodeView code;
+    const CodeView *codes;     // MODE_IPM, nullable: [nframes] a matrix per frame (same m and n)
     Opts o;
     Plan plan;
     int nframes;

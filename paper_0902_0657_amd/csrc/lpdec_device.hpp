@@ -450,9 +450,9 @@ struct Frame {
     int Z;                 // index of the zero slot of the PCG vector space (n + 2m)
     long long ticks_pcg;   // clock ticks spent inside pcg() during the current decode
 
-    LPD_INLINE void bind(const Args &a, char *hot, char *cold, Scratch *scr)
+    LPD_INLINE void bind(const Args &a, const CodeView &cv, char *hot, char *cold, Scratch *scr)
     {
-        cd = a.code; o = a.o; m = cd.m; n = cd.n; RW = a.plan.rw; CW = a.plan.cw;
+        cd = cv; o = a.o; m = cd.m; n = cd.n; RW = a.plan.rw; CW = a.plan.cw;
         RWC = RW / 8; CWC = CW / 4; MW = a.plan.maskwords;
         tid = threadIdx.x; nt = blockDim.x; sc = scr;
         ticks_pcg = 0;
@@ -900,19 +900,7 @@ struct Frame {
             // columns) were matched earlier, forward ones (the other rows of the row's column)
             // later
             __builtin_amdgcn_wave_barrier();
-            for (int step = 0; step < k; ++step) {
-                const int row = order[step];
-                int L = 0;
-                if (lane < RW) {
-                    const uint16_t e = rlist[(size_t)row * RW + lane];
-                    const int i = e != kEnd ? e_idx(e) : -1;
-                    const int pr = i >= 0 && i != pair[row] ? (int)pairrow[i] : -1;
-                    L = pr >= 0 ? lbv[pr] + 1 : 0;
-                }
-                L = wave_max_t(L);
-                if (lane == 0) lbv[row] = (int16_t)L;
-                __builtin_amdgcn_wave_barrier();
-            }
+            mts_row_back_levels(k);
             if (!expand) mts_row_fwd_levels(k);
             if (lane == 0) sc->i[1] = k;
         }
@@ -925,6 +913,27 @@ struct Frame {
             __syncthreads();
         }
         return pl;
+    }
+
+    // Back-substitution levels of the first k rows of order when A_M is lower triangular in
+    // that order: walking forward, a row's dependencies (the rows of its other matched columns)
+    // are already set. Wave 0.
+    LPD_INLINE void mts_row_back_levels(int k)
+    {
+        const int lane = tid & 63;
+        for (int step = 0; step < k; ++step) {
+            const int row = order[step];
+            int L = 0;
+            if (lane < RW) {
+                const uint16_t e = rlist[(size_t)row * RW + lane];
+                const int i = e != kEnd ? e_idx(e) : -1;
+                const int pr = i >= 0 && i != pair[row] ? (int)pairrow[i] : -1;
+                L = pr >= 0 ? lbv[pr] + 1 : 0;
+            }
+            L = wave_max_t(L);
+            if (lane == 0) lbv[row] = (int16_t)L;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 
     // Forward-substitution levels of the first k rows of order, walking backward (their
@@ -947,13 +956,169 @@ struct Frame {
         }
     }
 
-    // The preconditioning set of the context's PRECOND from the weights d2f: Algorithm 7 (1),
-    // Algorithm 8 with diagonal (2) or triangular (3) expansion, else the slack columns.
-    LPD_INLINE void find_precond_set()
+    // ------------------------------------------------------------ Algorithm 6 + Algorithm 5
+    // Column states of the incremental search, kept in rank[]: in M, candidate of the current
+    // test, matched by the current peeling.
+    static constexpr uint8_t kInM = 1, kCand = 2, kGone = 4;
+
+    // Triangulation Step (Algorithm 5) on S = the columns marked kInM or kCand: peeling in
+    // rounds. Each row with exactly one remaining column of S at the start of a round proposes
+    // that column; a column proposed by several rows goes to the lowest-indexed one, and every
+    // row of a matched column loses one degree. Rows matched in one round depend only on
+    // columns matched in earlier rounds, so any order within a round keeps A_S lower
+    // triangular. Fills pair, pairrow (standard columns) and order. Returns the number of
+    // columns matched: |S| when the set passes.
+    LPD_INLINE int peel_set()
     {
+        int *rd = boff;            // remaining columns of S in each row
+        int *owner = (int *)s;     // lowest row proposing each column in the current round
+        int16_t *prop = lbv;       // column each row proposes in the current round
+        for (int c = tid; c < n + m; c += nt) {
+            rank[c] &= (uint8_t)(kInM | kCand);
+            owner[c] = 0x7FFFFFFF;
+            if (c < n) pairrow[c] = -1;
+        }
+        __syncthreads();
+        for (int j = tid; j < m; j += nt) {
+            pair[j] = -1;
+            int d = 0;
+            if (cut(j)) {
+                d = rank[n + j] != 0;
+                for (int k = 0; k < RW; ++k) {
+                    const uint16_t e = rlist[(size_t)j * RW + k];
+                    d += e != kEnd && rank[e_idx(e)] != 0;
+                }
+            }
+            rd[j] = d;
+        }
+        if (tid == 0) sc->i[3] = 0;
+        __syncthreads();
+        int matched = 0;
+        for (;;) {
+            for (int j = tid; j < m; j += nt) {
+                int c = -1;
+                if (pair[j] < 0 && rd[j] == 1) {
+                    if (rank[n + j] == kInM || rank[n + j] == kCand) c = n + j;
+                    for (int k = 0; k < RW; ++k) {
+                        const uint16_t e = rlist[(size_t)j * RW + k];
+                        const int i = e != kEnd ? e_idx(e) : 0;
+                        if (e != kEnd && (rank[i] == kInM || rank[i] == kCand)) c = i;
+                    }
+                    if (c >= 0) atomicMin(&owner[c], j);
+                }
+                prop[j] = (int16_t)c;
+            }
+            __syncthreads();
+            for (int j = tid; j < m; j += nt) {
+                const int c = prop[j];
+                if (c < 0 || owner[c] != j) continue;
+                pair[j] = (int16_t)c;
+                order[atomicAdd(&sc->i[3], 1)] = (int16_t)j;
+                rank[c] |= kGone;
+                if (c >= n) {
+                    atomicSub(&rd[c - n], 1);
+                } else {
+                    pairrow[c] = (int16_t)j;
+                    for (int k = 0; k < CW; ++k) {
+                        const uint16_t e = clist[(size_t)c * CW + k];
+                        if (e != kEnd) atomicSub(&rd[e_idx(e)], 1);
+                    }
+                }
+            }
+            __syncthreads();
+            const int tot = sc->i[3];
+            if (tot == matched) break;
+            matched = tot;
+        }
+        __syncthreads();
+        return matched;
+    }
+
+    // Marks srt[pos + t], t < kk, as candidates for t < cand and with state `rest` otherwise.
+    LPD_INLINE void inc_mark(const uint16_t *srt, int pos, int kk, int cand, uint8_t rest)
+    {
+        __syncthreads();
+        for (int t = tid; t < kk; t += nt) rank[srt[pos + t]] = t < cand ? kCand : rest;
+        __syncthreads();
+    }
+
+    // Incremental greedy search for the triangular set (Algorithm 6): the LP's columns in key
+    // order (weight descending, index ascending), each added to M while M with it passes the
+    // Triangulation Step, until M has p columns. Equivalent batched form (Sec. V-C adds
+    // several columns per call): a block of the next kk columns is tested at once; if M with
+    // the whole block passes, so does M with every prefix of it, and all are added; otherwise
+    // bisection finds the shortest failing prefix, whose columns before the last are added and
+    // whose last column is dropped, exactly as one-at-a-time testing would. The block doubles
+    // after a pass and halves after a failure. Fills pair, pairrow, order, lbv, lfv; A_M is
+    // lower triangular in matching order. Returns p; calls counts Triangulation Steps.
+    LPD_INLINE int mts_inc(const float *wk, int &calls)
+    {
+        uint16_t *srt = lcol;
+        int pl = 0, ql = 0;
+        for (int j = tid; j < m; j += nt) pl += cut(j);
+        for (int c = tid; c < n + m; c += nt) {
+            rank[c] = 0;
+            if (c < n) pairrow[c] = -1;
+            if (!present(c)) continue;
+            ++ql;
+            const unsigned long long kc = colkey(wk, c);
+            int r = 0;
+            for (int c2 = 0; c2 < n + m; ++c2) r += present(c2) && colkey(wk, c2) > kc;
+            srt[r] = (uint16_t)c;
+        }
+        for (int j = tid; j < m; j += nt) { pair[j] = -1; lbv[j] = -1; lfv[j] = -1; }
+        pl = block_sum1(pl, sc);
+        ql = block_sum1(ql, sc);
+        p = pl;
+        int msz = 0, pos = 0, blk = 16;
+        calls = 0;
+        while (msz < pl && pos < ql) {
+            const int kk = min(min(blk, ql - pos), pl - msz);
+            inc_mark(srt, pos, kk, kk, 0);
+            ++calls;
+            if (peel_set() == msz + kk) {
+                inc_mark(srt, pos, kk, 0, kInM);
+                msz += kk;
+                pos += kk;
+                blk *= 2;
+                continue;
+            }
+            int lo = 0, hi = kk;   // M with the first lo passes, with the first hi fails
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                inc_mark(srt, pos, kk, mid, 0);
+                ++calls;
+                if (peel_set() == msz + mid) lo = mid;
+                else hi = mid;
+            }
+            // the first lo columns join M, column lo is dropped, the rest wait for later tests
+            inc_mark(srt, pos, kk, 0, 0);
+            if (lo > 0) inc_mark(srt, pos, lo, 0, kInM);
+            msz += lo;
+            pos += lo + 1;
+            blk = max(1, kk >> 1);
+        }
+        // the pairing of the final set, then the levels of the lower-triangular solves
+        peel_set();
+        if (tid < 64) {
+            mts_row_back_levels(msz);
+            mts_row_fwd_levels(msz);
+        }
+        __syncthreads();
+        return pl;
+    }
+
+    // The preconditioning set of the context's PRECOND from the weights d2f: Algorithm 7 (1),
+    // Algorithm 8 with diagonal (2) or triangular (3) expansion, Algorithm 6 (5), else the
+    // slack columns.
+    LPD_INLINE int find_precond_set()
+    {
+        int calls = 0;
         if (o.precond == 1) mts(nullptr);
         else if (o.precond == 2 || o.precond == 3) mts_row(nullptr, o.precond - 2);
+        else if (o.precond == 5) mts_inc(nullptr, calls);
         else slack_basis();
+        return calls;
     }
 
     // The slack columns as preconditioning set (A_M = I): used when Algorithm 7 is off.
@@ -1035,6 +1200,31 @@ struct Frame {
             }
         }
         __syncthreads();
+        // boff[L] / foff[L] now end level L; mark the levels that fit one pass of wave 0
+        if (tid < 64) {
+            mark_small(boff, nlb, 64 / RW);
+            mark_small(foff, nlf, 64 / CW);
+        }
+        __syncthreads();
+    }
+
+    // Wave 0: sets kSmallLevel on the level ends off[0..nlev) of levels with at most `fit` slots.
+    LPD_INLINE void mark_small(int *off, int nlev, int fit)
+    {
+        const int lane = tid & 63;
+        for (int base = 0; base < nlev; base += 64) {
+            const int L = base + lane;
+            bool small = false;
+            int e = 0;
+            if (L < nlev) {
+                e = off[L] & kOffMask;
+                const int s0 = L ? (off[L - 1] & kOffMask) : 0;
+                small = e - s0 <= fit;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (L < nlev && small) off[L] = e | kSmallLevel;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 
     // ------------------------------------------------------------ triangular solves
@@ -1048,6 +1238,14 @@ struct Frame {
     // finish needs (pre), the group sums the values with DPP, and the header lane finishes
     // the row. Levels are separated by a barrier; level bounds are read two levels ahead and
     // each lane's entry of the next level one level ahead.
+    //   A level with at most 64 / G slots fits one pass of wave 0. A run of such levels (the
+    // long dependency chains of late interior-point iterations are mostly single rows) is
+    // swept by wave 0 alone: its LDS accesses are processed in program order, so a level
+    // needs only the wait for the previous level's stores, not a workgroup barrier; the other
+    // waves meet wave 0 at the end of the run. build_levels() marks such levels in off[].
+    static constexpr int kSmallLevel = 1 << 30;
+    static constexpr int kOffMask = kSmallLevel - 1;
+
     template <int G, typename T, typename GF, typename PF, typename FF>
     LPD_INLINE void gsweep(const uint16_t *slots, const int *off, int nlev, GF gather, PF pre, FF finish)
     {
@@ -1060,18 +1258,50 @@ struct Frame {
             const T sum = gsum<G>(v);
             finish(valid && q == 0, e, pc, sum);
         };
-        int k0 = 0, k1 = off[0], k2 = nlev > 1 ? off[1] : k1;
-        uint16_t cur = g < k1 ? slots[g * G + q] : zero;
-        for (int L = 0; L < nlev; ++L) {
-            const int k3 = L + 2 < nlev ? off[L + 2] : k2;
-            const uint16_t nxt = k1 + g < k2 ? slots[(k1 + g) * G + q] : zero;
-            step(k0 + g < k1, cur);
-            for (int kb = k0 + ng; kb < k1; kb += ng) {
+        int L = 0, kA = 0, raw = off[0];
+        uint16_t cur = !(raw & kSmallLevel) && g < (raw & kOffMask) ? slots[g * G + q] : zero;
+        while (L < nlev) {
+            if (raw & kSmallLevel) {
+                if (tid < 64) {
+                    int l = L, a = kA, b = raw & kOffMask;
+                    uint16_t e = a + g < b ? slots[(a + g) * G + q] : zero;
+                    for (;;) {
+                        const int nraw = l + 1 < nlev ? off[l + 1] : 0;
+                        const bool more = (nraw & kSmallLevel) != 0;
+                        const int nb = nraw & kOffMask;
+                        const uint16_t en = more && b + g < nb ? slots[(b + g) * G + q] : zero;
+                        step(a + g < b, e);
+                        if (!more) break;
+                        // the level's stores complete before the next level's gathers
+                        __builtin_amdgcn_s_waitcnt(0xc07f);
+                        __builtin_amdgcn_wave_barrier();
+                        ++l;
+                        a = b;
+                        b = nb;
+                        e = en;
+                    }
+                    if (tid == 0) sc->i[4] = l + 1;
+                }
+                __syncthreads();
+                L = sc->i[4];
+                kA = L > 0 ? off[L - 1] & kOffMask : 0;
+                raw = L < nlev ? off[L] : 0;
+                cur = L < nlev && !(raw & kSmallLevel) && kA + g < (raw & kOffMask) ? slots[(kA + g) * G + q] : zero;
+                continue;
+            }
+            const int kB = raw & kOffMask;
+            const int nraw = L + 1 < nlev ? off[L + 1] : 0;
+            const uint16_t nxt = L + 1 < nlev && !(nraw & kSmallLevel) && kB + g < (nraw & kOffMask)
+                                     ? slots[(kB + g) * G + q] : zero;
+            step(kA + g < kB, cur);
+            for (int kb = kA + ng; kb < kB; kb += ng) {
                 const int k = kb + g;
-                step(k < k1, k < k1 ? slots[k * G + q] : zero);
+                step(k < kB, k < kB ? slots[k * G + q] : zero);
             }
             __syncthreads();
-            k0 = k1; k1 = k2; k2 = k3;
+            ++L;
+            kA = kB;
+            raw = nraw;
             cur = nxt;
         }
     }
@@ -1900,8 +2130,9 @@ struct Frame {
             // the reuse across iterations that Sec. V-C leaves open
             const long long t0 = wall_clock64();
             const bool search = it % o.mts_reuse == 0;
+            int tri_calls = 0;
             if (!direct_mode && search) {
-                find_precond_set();
+                tri_calls = find_precond_set();
                 build_levels();
                 st.max_levels = max(st.max_levels, max(nlb, nlf));
             }
@@ -1925,7 +2156,7 @@ struct Frame {
             const long long t2 = wall_clock64();
             st.ticks_mts += t1 - t0;
             st.ticks_solve += t2 - t1;
-            st.mts_rounds += o.precond && !direct_mode && search ? p : 0;
+            st.mts_rounds += o.precond && !direct_mode && search ? (o.precond == 5 ? tri_calls : p) : 0;
             st.pcg_iters += pits;
             st.pcg_rows += (long long)pits * p;
             st.ipm_cols += n + p;

@@ -116,14 +116,16 @@ LPD_INLINE void run_mts(Frame<PT> &F, const Args &a, int f)
     for (int i = F.tid; i < n; i += F.nt) F.sg[i] = 1;
     __syncthreads();
     F.build_lists();
+    int rounds = 0;
     if (a.o.precond == 2 || a.o.precond == 3) F.mts_row(a.w_in + (size_t)f * (n + m), a.o.precond - 2);
-    else F.mts(a.w_in + (size_t)f * (n + m));
+    else if (a.o.precond == 5) F.mts_inc(a.w_in + (size_t)f * (n + m), rounds);
+    else rounds = F.mts(a.w_in + (size_t)f * (n + m));
     for (int j = F.tid; j < m; j += F.nt) {
         a.i_out[(size_t)f * m + j] = F.pair[j];
         a.i_out2[(size_t)f * m + j] = F.lbv[j];
         a.i_out3[(size_t)f * m + j] = F.lfv[j];
     }
-    if (F.tid == 0 && a.flag) a.flag[f] = F.p;
+    if (F.tid == 0 && a.flag) a.flag[f] = a.o.precond == 5 ? rounds : F.p;
 }
 
 template <typename PT>
@@ -215,7 +217,8 @@ __global__ void __launch_bounds__(256) lpdec_main(Args a)
     char *hot = HOT_LDS ? lds_dyn : a.hot_ws + (size_t)f * a.hot_stride;
     char *cold = a.cold_ws + (size_t)f * a.cold_stride;
     Frame<PT> F;
-    F.bind(a, hot, cold, &sc);
+    // MODE_IPM may give every frame its own matrix (ALP: one LP row per cut)
+    F.bind(a, a.codes ? a.codes[f] : a.code, hot, cold, &sc);
     // tiles of the dense fallback follow the hot arena in dynamic LDS
     F.ldsd = a.plan.dense_on ? (double *)(lds_dyn + (HOT_LDS ? lp_align(a.plan.hot_bytes) : 0)) : nullptr;
     if constexpr (MODE == MODE_DECODE) {

@@ -155,7 +155,8 @@ def test_edge_cases(ctx, orc):
 
 
 @pytest.mark.parametrize("opt,val", [("MTS_REUSE", 2), ("MTS_REUSE", 4), ("WARM_START", 1), ("PRECOND", 2),
-                                     ("PRECOND", 3), ("PRECOND", 4), ("PRECOND", 0)])
+                                     ("PRECOND", 3), ("PRECOND", 4), ("PRECOND", 0),
+                                     ("PRECOND", 5)])
 def test_preconditioner_reuse_and_warm_start(ctx, orc, opt, val):
     """The preconditioning set kept over several IPM iterations of an LP (MTS_REUSE), each
     Newton solve started from the previous direction (WARM_START), or the preconditioner

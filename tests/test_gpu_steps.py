@@ -126,6 +126,33 @@ def test_mts_rowwise_pairing_and_levels_bit_exact(ctx, orc, n, kind, expand):
         assert np.array_equal(lb[f], lbo) and np.array_equal(lf[f], lfo), f
 
 
+@pytest.mark.parametrize("n,kind", [(96, "uniform"), (96, "ties"), (96, "spread"), (1024, "uniform"),
+                                    (1024, "ties"), (1024, "spread"), (4096, "spread")])
+def test_mts_incremental_pairing_and_levels_bit_exact(ctx, orc, n, kind):
+    """Algorithm 6 with the Triangulation Step of Algorithm 5 (PRECOND 5): the chosen set, the
+    row each column is matched with and both level schedules equal the oracle's."""
+    import torch
+    code = regular_code(n)
+    C = _code(ctx, code)
+    rng = np.random.Generator(np.random.PCG64(13 + n))
+    nf = 6 if n < 4096 else 2
+    hascut = (rng.random((nf, code.m)) < rng.uniform(0.5, 1.0, (nf, 1))).astype(np.uint8)
+    hascut[0] = 1
+    W = _weights(rng, nf, code.n + code.m, kind)
+    ctx.set_option("PRECOND", 5)
+    try:
+        pair, lb, lf, calls = ctx.mts_batch(C, cuda(hascut, torch.uint8), cuda(W, torch.float32))
+    finally:
+        ctx.set_option("PRECOND", 1)
+    pair, lb, lf, calls = host(pair), host(lb), host(lf), host(calls)
+    for f in range(nf):
+        po, order, _ = orc.mts_inc(code, hascut[f], W[f])
+        lbo, lfo = orc.mts_levels_any(code, hascut[f], po)
+        assert np.array_equal(pair[f], po), f
+        assert np.array_equal(lb[f], lbo) and np.array_equal(lf[f], lfo), f
+        assert calls[f] >= 1
+
+
 def _lp_case(orc, code, seed, snr=1.5):
     gamma = awgn_llr(code.n, snr, 1 - code.m / code.n, frame_seed(seed, 0, 0))
     res = orc.decode(code, gamma, trace=True)
