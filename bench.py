@@ -230,6 +230,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _collect(srv, tickets, label, every_s=20.0):
+    """Polls every ticket until all have a result (the server hands results out as frames
+    finish), printing progress while frames are outstanding. Returns {ticket: result}."""
+    done, last = {}, time.perf_counter()
+    while len(done) < len(tickets):
+        for t, n, _, _ in tickets:
+            if t not in done:
+                r = srv.poll(t, n)
+                if r is not None:
+                    done[t] = r
+        if len(done) < len(tickets):
+            if time.perf_counter() - last > every_s:
+                log(f"{label}: {len(done)} of {len(tickets)} requests done")
+                last = time.perf_counter()
+            time.sleep(0.005)
+    return done
+
+
 def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
     """Poisson arrivals at qps for `seconds`, then drain. Latency = submit to result."""
     from synth.channel import awgn_llr, frame_seed
@@ -245,11 +263,11 @@ def _poisson(srv, Cs, codes, rng, qps, seconds, stream_id):
             k += 1
             t_next += rng.exponential(1.0 / qps)
         time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
-    srv.drain()
+    res = _collect(srv, tickets, f"poisson {qps:.1f} qps")
     wall = time.perf_counter() - t0
     lat, per, fails = [], {}, []
     for t, n, e, seed in tickets:
-        r = srv.poll(t, n)
+        r = res[t]
         lat.append(r[3])
         per.setdefault(n, []).append(r[3])
         if r[1] < 0:
@@ -283,7 +301,9 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1
         ctx.set_option("SERVER_STREAMS", streams)
     prev = ctx.get_option("SERVER_MODE")
     ctx.set_option("SERVER_MODE", mode)
-    srv = ctx.server(hbm_budget_bytes=8 << 30, max_slots=2048)
+    # the large codes' engines hold a dense-fallback matrix per workgroup (34 MB at n=4096,
+    # 134 MB at n=8192): the full mix gets a larger share of the 288 GB
+    srv = ctx.server(hbm_budget_bytes=(64 << 30) if full else (8 << 30), max_slots=2048)
     ctx.set_option("SERVER_MODE", prev)
     try:
         t0 = time.perf_counter()
@@ -293,17 +313,21 @@ def serving(ctx, seconds=8.0, qps=40.0, seed=5, full=False, streams=None, mode=1
             e = float(rng.uniform(1.5, 3.0))
             g = awgn_llr(codes[ci].n, e, 0.5, frame_seed(78, ci, k))
             tk.append((srv.submit(Cs[ci], g), codes[ci].n, e, (78, ci, k)))
-        srv.drain()
+        res_b = _collect(srv, tk, f"burst of {burst}")
         sat = burst / (time.perf_counter() - t0)
         burst_fails = []
+        burst_lat = {}
         for t, n, e, seed in tk:
-            r = srv.poll(t, n)
+            r = res_b[t]
+            burst_lat.setdefault(n, []).append(r[3])
             if r[1] < 0:
                 burst_fails.append({"n": n, "flag": int(r[1]), "ebn0_db": e, "frame_seed": list(seed)})
         log(f"serving mode {mode}: burst of {burst} at {sat:.0f} frames/s")
-        res = _poisson(srv, Cs, codes, rng, qps, seconds, 77)
-        log(f"serving mode {mode}: {qps:.0f} qps p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
-        res.update({"mode": "persistent" if mode else "waves", "codes": [c.name for c in codes],
+        res = _poisson(srv, Cs, codes, rng, qps, seconds, 77) if qps > 0 else {}
+        if qps > 0:
+            log(f"serving mode {mode}: {qps:.0f} qps p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+        res.update({"burst_latency_max_s": {str(n): float(max(v)) for n, v in sorted(burst_lat.items())},
+                    "mode": "persistent" if mode else "waves", "codes": [c.name for c in codes],
                     "streams": int(ctx.get_option("SERVER_STREAMS")) if mode == 0 else len(codes),
                     "saturated_frames_per_s": sat, "burst": burst, "burst_failure_flags": burst_fails,
                     "at_fraction_of_saturated": [dict(fraction=f, **_poisson(srv, Cs, codes, rng, f * sat, seconds,
@@ -692,11 +716,15 @@ def main():
     }
     # serving first among the extra legs, while the process holds no other device work
     if not args.no_serve:
-        kw = dict(full=True, seconds=4.0, qps=10.0, burst=128) if args.serve_full else {}
-        res["serving"] = serving(ctx, mode=1, **kw)
-        log(f"serving: {res['serving']['requests']} requests")
-        res["serving_waves"] = serving(ctx, mode=0, **kw)
-        log(f"serving (waves): {res['serving_waves']['requests']} requests")
+        if args.serve_full:
+            # the irregular n=8192 code's fractional frames take about 2 minutes each over AWGN
+            # (hundreds of dense solves at p up to 4096): a burst of 64 gives the saturated rate,
+            # then 20 s of arrivals at each fraction of it, each drained
+            res["serving"] = serving(ctx, mode=1, full=True, seconds=20.0, qps=0.0, burst=64)
+        else:
+            res["serving"] = serving(ctx, mode=1)
+            res["serving_waves"] = serving(ctx, mode=0)
+        log("serving done")
     if not args.no_legs:
         # the method alone: no dense fallback, FP64 PCG with a fixed cap of 2000 iterations
         legs = [("method_only", {"DIRECT_FALLBACK": 0, "PCG_MAXIT": 2000, "PRECISION": 1}),

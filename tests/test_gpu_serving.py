@@ -81,3 +81,38 @@ def test_persistent_engine_leaves_when_idle_and_returns():
         assert r is not None, k
         assert r[1] == int(fl[k]) and np.array_equal(r[0], xh[k]) and r[2] == float(ob[k])
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_large_codes_in_the_mix_match_alone(mode):
+    """The serving mix's large codes, (3,6) n=4096 and the irregular n=8192 code, beside n=256
+    and n=1024 (Eb/N0 2.5-3.5 dB, so that every frame finishes in seconds): each result is
+    bit-identical to the same frame decoded alone. The 1 GiB budget admits only a few
+    workgroups for the large codes (their dense-fallback matrices take 34 and 134 MB per
+    workgroup), so their requests queue for each other."""
+    import torch
+    from paper_0902_0657_amd import Code
+    ctx = make_ctx(SERVER_MODE=mode)
+    codes = [regular_code(256), regular_code(1024), regular_code(4096), irregular_code(8192)]
+    Cs = [Code.from_synth(ctx, c) for c in codes]
+    rng = np.random.Generator(np.random.PCG64(12))
+    reqs = []
+    srv = ctx.server(hbm_budget_bytes=1 << 30, max_slots=64)
+    try:
+        for k in range(24):
+            ci = k % len(codes)
+            g = awgn_llr(codes[ci].n, float(rng.uniform(2.5, 3.5)), 0.5, frame_seed(124, ci, k))
+            reqs.append((srv.submit(Cs[ci], g), ci, g))
+        print(f"[serving mode {mode}] 24 requests submitted", flush=True)
+        srv.drain()
+        got = [srv.poll(t, codes[ci].n) for t, ci, _ in reqs]
+    finally:
+        srv.close()
+    for (t, ci, g), r in zip(reqs, got):
+        assert r is not None, t
+        xh, fl, ob, lat = r
+        out = ctx.decode_batch(Cs[ci], cuda(g[None, :], torch.float64))
+        torch.cuda.synchronize()
+        assert fl == int(host(out["flag"])[0]) and np.array_equal(xh, host(out["xhat"])[0]), (t, ci)
+        assert ob == float(host(out["obj"])[0])
+    ctx.close()
