@@ -631,8 +631,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
-                    help="PCG vector precision of the main leg (fp32: the n=1024 workload's FP32-PCG form)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp64",
+                    help="PCG vector precision of the main leg (fp64, the library's default: with FP32 "
+                         "vectors PCG finishes far fewer of the late Newton systems within the cap; "
+                         "the FP32 form is the other_precision leg)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the method-only and other-precision legs")
@@ -704,9 +706,9 @@ def main():
                                "(171/171/170 frames), FP32 LLRs, 512 frames per launch, MALP-A; Newton systems "
                                "by " + ("FP64" if fp64 else "FP32") + " PCG (Algorithm 4, Algorithm 7 "
                                "preconditioner) with FP64 refinement; a system PCG does not finish within "
-                               "max(100, p^2/3500) iterations, and the rest of its LP's systems, go to a dense "
-                               "FP64 Cholesky on the matrix cores (hybrid; share in decode_stats, the method "
-                               "alone in method_only)",
+                               "max(300, p^2/3500) iterations, and the rest of its LP's systems, go to a dense "
+                               "FP64 Cholesky on the matrix cores (share in main.decode_stats."
+                               "newton_solved_by_pcg; the method alone in method_only)",
                    "global_batch": nf, "parallelism": "one workgroup per frame"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "batch mode: a frame's result is available when its launch ends"},

@@ -107,7 +107,7 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *   ETA            fraction-to-boundary factor of the step lengths (0.9995)
  *   PCG_TOL        PCG stops at ||r|| <= PCG_TOL ||rhs|| (1e-6)
  *   PCG_MAXIT      PCG iteration cap per round; 0 (default) = automatic: with the dense
- *                  fallback, min(2000, max(100, p^2 / 3500)) for an LP of p rows (p^2 / 3500
+ *                  fallback, min(2000, max(300, p^2 / 3500)) for an LP of p rows (p^2 / 3500
  *                  is about the PCG iterations that cost as much as two dense solves), else
  *                  500. With the
  *                  fallback on, a round inside the IPM that reaches the cap ends the PCG

@@ -1263,13 +1263,19 @@ struct Frame {
         while (L < nlev) {
             if (raw & kSmallLevel) {
                 if (tid < 64) {
+                    // level l: slots [a, b) with entry e; the end of level l + 1 (raw1) is known
+                    // one level ahead and its first entry is loaded during level l, so that
+                    // the only dependent LDS access on the chain is the gather of a level
+                    // (bounds are the same in every lane: readfirstlane keeps them in scalar
+                    // registers, so the loop control is scalar)
                     int l = L, a = kA, b = raw & kOffMask;
                     uint16_t e = a + g < b ? slots[(a + g) * G + q] : zero;
+                    int raw1 = __builtin_amdgcn_readfirstlane(l + 1 < nlev ? off[l + 1] : 0);
                     for (;;) {
-                        const int nraw = l + 1 < nlev ? off[l + 1] : 0;
-                        const bool more = (nraw & kSmallLevel) != 0;
-                        const int nb = nraw & kOffMask;
+                        const bool more = (raw1 & kSmallLevel) != 0;
+                        const int nb = raw1 & kOffMask;
                         const uint16_t en = more && b + g < nb ? slots[(b + g) * G + q] : zero;
+                        const int raw2 = __builtin_amdgcn_readfirstlane(more && l + 2 < nlev ? off[l + 2] : 0);
                         step(a + g < b, e);
                         if (!more) break;
                         // the level's stores complete before the next level's gathers
@@ -1279,6 +1285,7 @@ struct Frame {
                         a = b;
                         b = nb;
                         e = en;
+                        raw1 = raw2;
                     }
                     if (tid == 0) sc->i[4] = l + 1;
                 }
@@ -1487,18 +1494,18 @@ struct Frame {
     }
 
     // PCG iteration cap of one round. PCG_MAXIT > 0 is used as given; 0 (automatic) gives a
-    // PCG attempt at least 100 iterations, which is enough for the early IPM systems of
-    // every LP, and for large LPs about twice the cost of the dense fallback (one dense solve
-    // costs about p^2 / 7000 PCG iterations: its work grows as p^3, a PCG iteration's as p);
-    // 500 without the fallback. Inside the IPM a round that reaches the cap hands the system
-    // to the dense solve.
+    // PCG attempt at least 300 iterations, with which PCG finishes about nine in ten Newton
+    // systems of the n=1024 workload (FP64 vectors), and for large LPs about twice the cost of
+    // the dense fallback (one dense solve costs about p^2 / 7000 PCG iterations: its work grows
+    // as p^3, a PCG iteration's as p); 500 without the fallback. Inside the IPM a round that
+    // reaches the cap hands the system to the dense solve.
     LPD_INLINE int pcg_cap() const
     {
         if (o.pcg_maxit > 0) return o.pcg_maxit;
         if (!qd) return 500;
         const double pp = (double)p;
         const double cap = pp * pp / 3500.0;
-        return cap < 100.0 ? 100 : (cap > 2000.0 ? 2000 : (int)cap);
+        return cap < 300.0 ? 300 : (cap > 2000.0 ? 2000 : (int)cap);
     }
 
     // One refinement round in precision T: r = L^-1 rho, PCG, dy += L^-T v (transforms in
