@@ -194,6 +194,16 @@ LPD_INLINE uint32_t wave_max_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// max over lanes 0..15 (row 0) for every lane: row_shr scan, then lane 15
+LPD_INLINE uint32_t row16_max_u32(uint32_t v)
+{
+    v = op_max_u(v, dpp<0x111, 0xF>(0u, v));
+    v = op_max_u(v, dpp<0x112, 0xF>(0u, v));
+    v = op_max_u(v, dpp<0x114, 0xF>(0u, v));
+    v = op_max_u(v, dpp<0x118, 0xF>(0u, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+}
+
 // max of 64-bit keys: high words first, then the low words of the lanes holding that high word
 LPD_INLINE unsigned long long wave_max_u64(unsigned long long k)
 {
@@ -664,30 +674,18 @@ struct Frame {
                 const unsigned long long K = wave_max_u64(mine);
                 if (K == 0ull) break;   // no degree-1 column: cannot happen while rows remain
                 const int c = mts_key_col(K);
-                // the row of c: its only live row; the other rows give the forward level
+                // the row of c: its only live row; the other rows give the forward level.
+                // Lane k < CW reads entry k of the column's list (CW <= 16)
                 int row = c - n, L = 0;
                 if (c < n) {
-                    row = -1;
-                    for (int ch = 0; ch < CWC; ++ch) {
-                        Ch4 E;
-                        ldch(E, clist + (size_t)c * CW + 4 * ch);
-                        int pj[4], lj[4];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint16_t e = at(E, k);
-                            const int j = e != kEnd ? e_idx(e) : 0;
-                            pj[k] = pair[j];
-                            lj[k] = lfv[j];
-                        }
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint16_t e = at(E, k);
-                            const bool ok = e != kEnd;
-                            row = ok && pj[k] < 0 ? e_idx(e) : row;
-                            L = ok && pj[k] >= 0 ? max(L, lj[k] + 1) : L;
-                        }
-                    }
-                    if (row < 0) break;   // a degree-1 column always has its live row
+                    const uint16_t ce = lane < CW ? clist[(size_t)c * CW + lane] : kEnd;
+                    const bool okc = ce != kEnd;
+                    const int jc = okc ? e_idx(ce) : 0;
+                    const int pjc = pair[jc], ljc = lfv[jc];
+                    const unsigned long long live = __ballot(okc && pjc < 0);
+                    if (!live) break;   // a degree-1 column always has its live row
+                    row = __builtin_amdgcn_readlane(jc, __ffsll((long long)live) - 1);
+                    L = (int)row16_max_u32(okc && pjc >= 0 ? (uint32_t)(ljc + 1) : 0u);
                 }
                 // everything the updates read, loaded together
                 const uint16_t e = rlist[(size_t)row * RW + le];
@@ -930,7 +928,7 @@ struct Frame {
                 const int pr = i >= 0 && i != pair[row] ? (int)pairrow[i] : -1;
                 L = pr >= 0 ? lbv[pr] + 1 : 0;
             }
-            L = wave_max_t(L);
+            L = (int)row16_max_u32((uint32_t)L);
             if (lane == 0) lbv[row] = (int16_t)L;
             __builtin_amdgcn_wave_barrier();
         }
@@ -950,7 +948,7 @@ struct Frame {
                 const int jj = e != kEnd ? e_idx(e) : -1;
                 L = jj >= 0 && jj != row ? lfv[jj] + 1 : 0;
             }
-            L = wave_max_t(L);
+            L = (int)row16_max_u32((uint32_t)L);
             if (lane == 0) lfv[row] = (int16_t)L;
             __builtin_amdgcn_wave_barrier();
         }
@@ -1278,8 +1276,11 @@ struct Frame {
                         const int raw2 = __builtin_amdgcn_readfirstlane(more && l + 2 < nlev ? off[l + 2] : 0);
                         step(a + g < b, e);
                         if (!more) break;
-                        // the level's stores complete before the next level's gathers
-                        __builtin_amdgcn_s_waitcnt(0xc07f);
+                        // the next level's gathers must see the level's stores. In LDS they do
+                        // without a wait (the LDS executes one wave's instructions in issue
+                        // order); stores to global memory (arenas that do not fit in LDS) are
+                        // waited for (vmcnt 0, LDS counter untouched)
+                        __builtin_amdgcn_s_waitcnt(0x0f70);
                         __builtin_amdgcn_wave_barrier();
                         ++l;
                         a = b;
