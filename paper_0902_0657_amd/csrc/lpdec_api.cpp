@@ -916,7 +916,7 @@ hipError_t hostout_ensure(HostOut &o, size_t bytes)
 struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    Workspace ws;                 // kernel workspace of this lane
+    Workspace ws;                 // kernel workspace of the wave in flight (its admitted footprint)
     Workspace io;                 // gamma in
     HostOut out;                  // xhat | flag | obj | done of every frame of the wave
     std::vector<Request> wave;    // frames in flight on this lane
@@ -975,6 +975,27 @@ struct lpdec_server {
 
 namespace {
 
+// A server lane's device memory: stream-ordered allocation on the lane's stream, freed on that
+// stream when the wave retires, so that the memory held matches the admitted footprints.
+hipError_t lane_alloc(Workspace &w, size_t bytes, hipStream_t stream)
+{
+    w.ptr = nullptr;
+    w.bytes = 0;
+    w.fixed = true;
+    const hipError_t e = hipMallocAsync((void **)&w.ptr, bytes ? bytes : 1, stream);
+    if (e == hipSuccess) w.bytes = bytes;
+    else w.ptr = nullptr;
+    return e;
+}
+
+void lane_release(Lane &L)
+{
+    if (L.ws.ptr) (void)hipFreeAsync(L.ws.ptr, L.stream);
+    if (L.io.ptr) (void)hipFreeAsync(L.io.ptr, L.stream);
+    L.ws = Workspace{};
+    L.io = Workspace{};
+}
+
 size_t frame_footprint(const lpdec_code *c, int pt64)
 {
     Plan p = lpdec::make_plan(c->m, c->n, c->dcmax, c->dvmax, pt64 ? 8 : 4, c->ctx->opts.direct != 0);
@@ -1023,6 +1044,9 @@ void server_loop(lpdec_server *s)
                 ++L.nretired;
             }
             if (!ended) continue;
+            // the lane gives its device memory back with the wave's budget: stream-ordered
+            // frees on its own stream, which other lanes' kernels do not wait for
+            lane_release(L);
             freed_bytes += L.footprint;
             freed_slots += nf;
             L.wave.clear();
@@ -1078,7 +1102,11 @@ void server_loop(lpdec_server *s)
             const size_t out_bytes = off_d + 4 * (size_t)nf;
             std::vector<double> g((size_t)nf * n);
             for (int k = 0; k < nf; ++k) std::copy(L.wave[k].gamma.begin(), L.wave[k].gamma.end(), g.begin() + (size_t)k * n);
-            hipError_t e = ws_ensure(L.io, 8 * g.size());
+            // device memory exactly as admitted: the kernel workspace is the wave's footprint
+            // (a region the launch cannot grow) and the inputs their own bytes, both allocated on
+            // the lane's stream and released when the wave retires
+            hipError_t e = lane_alloc(L.ws, ln.need, L.stream);
+            if (e == hipSuccess) e = lane_alloc(L.io, 8 * g.size(), L.stream);
             if (e == hipSuccess) e = hostout_ensure(L.out, out_bytes);
             if (e == hipSuccess) {
                 // the lane is idle, so nothing reads the previous wave's flags any more
@@ -1116,6 +1144,7 @@ void server_loop(lpdec_server *s)
                 s->slots_in_use -= nf;
                 L.wave.clear();
                 L.busy = false;
+                lane_release(L);
                 s->err = "wave launch failed";
                 s->cv_done.notify_all();
             }
@@ -1487,9 +1516,10 @@ extern "C" lpdec_status lpdec_server_destroy(lpdec_server *s)
     if (s->worker.joinable()) s->worker.join();
     for (auto &E : s->engines) engine_free(*E);
     for (auto &L : s->lanes) {
-        if (L.stream) (void)hipStreamSynchronize(L.stream);
-        ws_free(L.ws);
-        ws_free(L.io);
+        if (L.stream) {
+            lane_release(L);
+            (void)hipStreamSynchronize(L.stream);
+        }
         if (L.out.h) (void)hipHostFree(L.out.h);
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.stream) (void)hipStreamDestroy(L.stream);
