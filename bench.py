@@ -143,10 +143,15 @@ def golden_parity(name, code, G, flags, xhat, objs):
             "source": f"tests/golden/{GOLDEN_FILES[name]} (oracle results)"}
 
 
+_WL = {}
+
+
 def _oracle_worker(args):
     name, f = args
     import oracle
-    code, G = workload(name)
+    if name not in _WL:
+        _WL[name] = workload(name)
+    code, G = _WL[name]
     t = time.perf_counter()
     r = oracle.decode(code, G[f].astype(np.float64))
     return time.perf_counter() - t, r.xhat, r.flag, r.objective
@@ -196,6 +201,42 @@ def cpu_baseline(name, frames, budget_s=20.0, max_workers=16):
                       f"{workers} worker processes, {wall:.1f} s wall",
             "single_thread_s_per_frame": float(np.mean([d[1][0] for d in done])),
             "host_cores": {"sched_getaffinity": avail, "lscpu": lscpu, "used": workers}}, done
+
+
+def cpu_sample_cutoff(name, frames, budget_s=90.0, max_workers=16):
+    """The oracle on the host cores for the large workloads, whose frames take minutes each: one
+    frame per worker process in index order, and every frame still running when the time
+    budget ends is abandoned (the workers are terminated). Rate = frames finished / budget."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
+    avail, lscpu = host_cores()
+    workers = max(1, min(avail, max_workers))
+    ctxp = mp.get_context("fork")
+    t0 = time.perf_counter()
+    done = []
+    pool = ctxp.Pool(workers)
+    try:
+        it = pool.imap_unordered(_oracle_worker, [(name, f) for f in frames])
+        while True:
+            left = budget_s - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                done.append(it.next(timeout=left))
+            except mp.TimeoutError:
+                break
+            except StopIteration:
+                break
+    finally:
+        pool.terminate()
+        pool.join()
+    wall = min(time.perf_counter() - t0, budget_s) if len(done) < len(frames) else time.perf_counter() - t0
+    return {"value": len(done) / wall, "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "sample": f"{name} frames in index order, one per worker process, {workers} workers; "
+                      f"{len(done)} finished within {wall:.0f} s, the rest abandoned at the cutoff",
+            "single_thread_s_per_frame": float(np.mean([d[0] for d in done])) if done else None,
+            "host_cores": {"sched_getaffinity": avail, "lscpu": lscpu, "used": workers}}
 
 
 def interleaved_c2(k):
@@ -529,13 +570,18 @@ def sources_digest():
     return h.hexdigest()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lpdec_main_n1024_traffic.md")
+PROFILE_TAGS = {"c2": "n1024", "c3": "n4096", "c4": "irr8192"}
 
 
-def stored_traffic():
+def traffic_file(name="c2"):
+    return os.path.join(ROOT, "profiles", f"lpdec_main_{PROFILE_TAGS[name]}_traffic.md")
+
+
+def stored_traffic(name="c2"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, when it was taken on
     the current sources (else None). The summary holds one JSON line starting with
     '{"traffic"'."""
+    TRAFFIC_FILE = traffic_file(name)
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     with open(TRAFFIC_FILE) as fh:
@@ -548,6 +594,73 @@ def stored_traffic():
     fetch = t["fetch_kib_per_launch"] * 1024.0 * t["fetch_scale"]
     write = t["write_kib_per_launch"] * 1024.0 * t["write_scale"]
     return fetch + write, "FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors"
+
+
+PROFILE_COMMANDS = {
+    "c2": "python bench.py --steps 1 --warmup 0 --no-cpu --no-plain --no-legs --no-serve",
+    "c3": "python bench.py --only-configs --configs c3 --no-cpu",
+    "c4": "python bench.py --only-configs --configs c4 --no-cpu",
+}
+PROFILE_TITLES = {"c2": "n=1024 (3,6) batch of 512 frames", "c3": "n=4096 (3,6) batch of 256 frames",
+                  "c4": "irregular n=8192 batch of 128 frames (BSC)"}
+
+
+def summarize_profiles(name, base):
+    """Writes profiles/lpdec_main_<tag>_kernel_stats.md and _traffic.md from the rocprofv3 CSV
+    output of the three runs of PROFILE_COMMANDS[name] (kernel trace, FETCH_SIZE, WRITE_SIZE)
+    under base/prof_<name>_{kt,fetch,write}/, and the benchmark line the kernel-trace run
+    printed (base/prof_<name>_kt.out)."""
+    import csv
+    tag, cmd, title = PROFILE_TAGS[name], PROFILE_COMMANDS[name], PROFILE_TITLES[name]
+    stats = list(csv.DictReader(open(os.path.join(base, f"prof_{name}_kt", "run_kernel_stats.csv"))))
+    line = [ln for ln in open(os.path.join(base, f"prof_{name}_kt.out")) if ln.startswith("{")][-1]
+    bench = json.loads(line)
+    if name == "c2":
+        leg, roof = bench["main"], bench["roofline"]
+    else:
+        leg = bench[f"config_{name}"]
+        roof = leg["roofline"]
+    out = [f"# lpdec_main, {title}: rocprofv3 kernel statistics", "",
+           "Command (from the repository root, on the GPU box):", "",
+           f"    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_{name}_kt -o run -- {cmd}", "",
+           "| kernel | calls | total ns | average ns | min ns | max ns | share % |", "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        out.append(f"| `{r['Name']}` | {r['Calls']} | {r['TotalDurationNs']} | {float(r['AverageNs']):.0f} | "
+                   f"{r['MinNs']} | {r['MaxNs']} | {float(r['Percentage']):.2f} |")
+    out += ["", f"bench.py in the same run: kernel time from HIP events {roof['kernel_ms']:.1f} ms, "
+                f"{leg['value']:.2f} frames/s; algorithmic bytes {roof['algorithmic_bytes_per_launch']:.4g} "
+                f"(PCG {roof['pcg_bytes_per_launch']:.4g}, IPM {roof['ipm_bytes_per_launch']:.4g}); "
+                f"PCG {roof['pcg_only']['us_per_iteration']:.1f} us per iteration; Newton systems solved by PCG "
+                f"{leg['decode_stats']['newton_solved_by_pcg']:.3f}; parity with the stored oracle frames: "
+                f"{leg['parity_vs_oracle']['mismatches']} of {leg['parity_vs_oracle']['frames']} differ.", ""]
+    open(os.path.join(ROOT, "profiles", f"lpdec_main_{tag}_kernel_stats.md"), "w").write("\n".join(out))
+    kib = {}
+    for cnt in ("fetch", "write"):
+        rows = list(csv.DictReader(open(os.path.join(base, f"prof_{name}_{cnt}", "run_counter_collection.csv"))))
+        main = [r for r in rows if r["Kernel_Name"].startswith("void lpdec::lpdec_main")]
+        copy = [r for r in rows if r["Kernel_Name"] == "__amd_rocclr_copyBuffer"]
+        kib[cnt] = (float(main[-1]["Counter_Value"]), max(float(r["Counter_Value"]) for r in copy))
+    copy_bytes = 256 << 20
+    fs = copy_bytes / 1024.0 / kib["fetch"][1]
+    ws = copy_bytes / 1024.0 / kib["write"][1]
+    hbm = kib["fetch"][0] * 1024 * fs + kib["write"][0] * 1024 * ws
+    alg = roof["algorithmic_bytes_per_launch"]
+    rec = {"traffic": {"sources_sha256": sources_digest(), "fetch_kib_per_launch": kib["fetch"][0],
+                       "write_kib_per_launch": kib["write"][0], "fetch_scale": fs, "write_scale": ws,
+                       "copy_fetch_kib": kib["fetch"][1], "copy_write_kib": kib["write"][1], "copy_bytes": copy_bytes}}
+    out = [f"# lpdec_main, {title}: HBM traffic counters", "", "Two counter runs (from the repository root, on the GPU box):", "",
+           f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_{name}_fetch -o run -- {cmd} --calib-copy",
+           f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_{name}_write -o run -- {cmd} --calib-copy", "",
+           "`--calib-copy` runs one 256 MiB device-to-device copy first; the counters of that copy",
+           "kernel give the scale factors (bytes moved / counter reading).", "",
+           "| counter | decode launch (KiB) | 256 MiB copy (KiB) | scale |", "|---|---|---|---|",
+           f"| FETCH_SIZE | {kib['fetch'][0]:.0f} | {kib['fetch'][1]:.0f} | {fs:.4f} |",
+           f"| WRITE_SIZE | {kib['write'][0]:.0f} | {kib['write'][1]:.0f} | {ws:.4f} |", "",
+           f"HBM bytes per decode launch: {hbm:.4g}; algorithmic bytes {alg:.4g}; counters / algorithmic = "
+           f"{hbm / alg:.3f}; {hbm / (roof['kernel_ms'] / 1e3) / 1e9:.0f} GB/s over the launch.", "",
+           "Machine-readable (bench.py uses it while the sources hash matches):", "", json.dumps(rec), ""]
+    open(os.path.join(ROOT, "profiles", f"lpdec_main_{tag}_traffic.md"), "w").write("\n".join(out))
+    print(f"{name}: counters {hbm:.4g} B, algorithmic {alg:.4g} B, ratio {hbm / alg:.3f}")
 
 
 def copy_calibration(dev, nbytes=256 << 20):
@@ -605,7 +718,7 @@ def leg_summary(name, ctx_opts, code, G, out, step_ms, ncu, elem, traffic=None, 
     }, st, flags, xhat, objs
 
 
-def config_leg(name, dev, stream, opts, label):
+def config_leg(name, dev, stream, opts, label, cpu=True):
     """One launch of a whole workload (c3: n=4096, 256 frames; c4: irregular n=8192, 128
     frames) with its roofline, parity on the stored oracle frames and decode statistics."""
     import torch
@@ -616,8 +729,12 @@ def config_leg(name, dev, stream, opts, label):
     g = torch.as_tensor(G, device=dev)
     out, step_ms, _ = run_leg(ctx, C, g, G.shape[0], dev, stream, 1, 0, f"{name} {label}")
     elem = 8 if int(ctx.get_option("PRECISION")) != 0 else 4
-    res, *_ = leg_summary(name, opts, code, G, out, step_ms, ctx_ncu(), elem)
+    traffic, note = stored_traffic(name)
+    res, *_ = leg_summary(name, opts, code, G, out, step_ms, ctx_ncu(), elem, traffic, note)
     ctx.close()
+    if cpu:
+        res["cpu_baseline"] = cpu_sample_cutoff(name, list(range(G.shape[0])))
+        log(f"{name} cpu sample: {res['cpu_baseline']['sample']}")
     return res
 
 
@@ -642,6 +759,10 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving mix over n = 256, 1024, 4096 and the irregular 8192 code")
     ap.add_argument("--configs", default="", help="comma list of extra whole-workload launches: c3, c4")
+    ap.add_argument("--summarize-profiles", default="",
+                    help="DIR: write the profiles/ summaries from rocprofv3 output under DIR (no GPU)")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="run only the --configs launches (for profiling them alone); prints their legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB copy first (HBM counter calibration under rocprofv3)")
     ap.add_argument("--block", type=int, default=0)
@@ -662,6 +783,21 @@ def main():
 
     if args.precond_study:
         print(json.dumps(precond_study()))
+        return
+    if args.summarize_profiles:
+        for name in ("c2", "c3", "c4"):
+            if os.path.exists(os.path.join(args.summarize_profiles, f"prof_{name}_kt")):
+                summarize_profiles(name, args.summarize_profiles)
+        return
+    if args.only_configs:
+        import torch
+        dev = torch.device("cuda:0")
+        stream = torch.cuda.current_stream(dev)
+        if args.calib_copy:
+            copy_calibration(dev)
+        opts = {"PRECISION": 1 if args.precision == "fp64" else 0}
+        print(json.dumps({f"config_{c}": config_leg(c, dev, stream, opts, "main", cpu=not args.no_cpu)
+                          for c in args.configs.split(",") if c}))
         return
     if args.precond_compare or args.alp_study:
         import torch
@@ -739,7 +875,7 @@ def main():
             log(f"{lname}: {msx.mean():.1f} ms")
             c2x.close()
     for name in [c for c in args.configs.split(",") if c]:
-        res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main")
+        res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main", cpu=not args.no_cpu)
         log(f"config {name}: {res[f'config_{name}']['ms_per_step']:.0f} ms")
     if not args.no_plain:
         frames = interleaved_c2(24)
