@@ -479,7 +479,7 @@ PRECOND_NAMES = {1: "Algorithm 7 (column-wise)", 2: "Algorithm 8 (row-wise, diag
                  0: "slack columns (diagonal)", 4: "CG (no preconditioner)"}
 
 
-def precond_compare(dev, stream, name="c2", preconds=(1, 2, 3, 5, 0, 4), method_only=False):
+def precond_compare(dev, stream, name="c2", preconds=(1, 2, 3, 5, 0, 4), method_only=False, only=None):
     """One launch of a whole workload per preconditioner: the share of Newton systems that PCG
     solves within the automatic cap (the rest go to the dense fallback), PCG iterations per
     PCG-solved system, search cost and launch time; with method_only, no dense fallback (FP64
@@ -490,7 +490,7 @@ def precond_compare(dev, stream, name="c2", preconds=(1, 2, 3, 5, 0, 4), method_
     code, G = workload(name)
     g = torch.as_tensor(G, device=dev)
     rows = []
-    for pc in preconds:
+    for pc in (only or preconds):
         opts = {"PRECOND": pc, "PRECISION": 1}
         if method_only:
             opts.update({"DIRECT_FALLBACK": 0, "PCG_MAXIT": 2000})
@@ -772,6 +772,7 @@ def main():
                     help="print the preconditioners' Newton-system shares on a whole workload (c2 or c3) instead "
                          "of the benchmark; with --method-only, without the dense fallback")
     ap.add_argument("--method-only", action="store_true")
+    ap.add_argument("--preconds", default="", help="comma list of PRECOND values for --precond-compare")
     ap.add_argument("--alp-study", action="store_true",
                     help="print ALP / MALP-A / MALP-B LP counts and sizes on the n=1024 batch (Sec. III-D)")
     args = ap.parse_args()
@@ -804,7 +805,9 @@ def main():
         dev = torch.device("cuda:0")
         stream = torch.cuda.current_stream(dev)
         if args.precond_compare:
-            print(json.dumps(precond_compare(dev, stream, args.precond_compare, method_only=args.method_only)))
+            only = [int(x) for x in args.preconds.split(",")] if args.preconds else None
+            print(json.dumps(precond_compare(dev, stream, args.precond_compare, method_only=args.method_only,
+                                             only=only)))
         if args.alp_study:
             print(json.dumps(alp_study(dev, stream)))
         return
