@@ -57,6 +57,10 @@ typedef int32_t lpdec_status;
                                         (impossible in exact arithmetic, Theorem 2b) */
 #define LPDEC_FLAG_ALP_CAPACITY (-6) /* ALP only: the LP outgrew the list encoding (a variable in
                                         more than 16 cuts, or more than 16383 - n cuts) */
+#define LPDEC_FLAG_CUT_CYCLE (-7)    /* MALP: the cut set of an LP recurred two LPs later (an
+                                        optimum that is not unique at the IPM's accuracy, against
+                                        the uniqueness Theorem 2 assumes); u, the decisions and
+                                        the objective are those of the costlier LP of the two */
 
 typedef struct lpdec_ctx lpdec_ctx;
 typedef struct lpdec_code lpdec_code;

@@ -55,6 +55,7 @@ typedef struct {
     double eps_stall;/* below it, an iteration that makes no progress ends the IPM */
     double tau_cost; /* a cost decrease beyond tau_cost (1 + |c^T x|) between LPs is a failure */
     int box_clamp;   /* 1: u^k is put back on [0, 1]^n before Algorithm 2 (tests set 0) */
+    int cycle_stop;  /* 1: a cut set that recurs two LPs later ends the decode (tests set 0) */
 } orc_opts;
 
 typedef struct {
@@ -62,7 +63,8 @@ typedef struct {
     int ipm_iters;       /* IPM iterations summed over LPs */
     int p_max;           /* largest number of cuts in one LP */
     int p_final;         /* cuts in the last LP */
-    int status;          /* 0 ok, -1 IPM cap, -3 MALP cap, -2 non-finite, -5 cost decrease */
+    int status;          /* 0 ok, -1 IPM cap, -3 MALP cap, -2 non-finite, -5 cost decrease,
+                            -7 cut cycle */
 } orc_stats;
 
 /* ------------------------------------------------------------------------------------ */
@@ -370,6 +372,10 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
         if (gamma[i] < 0.0) gneg += gamma[i];
     }
     double cost_prev = gneg;                          /* gamma^T u^(k-1) */
+    double cost_prev2 = gneg;                         /* gamma^T u^(k-2) */
+    uint32_t *mask1 = calloc(m, sizeof(uint32_t));    /* cut set of LP k-1 */
+    uint32_t *mask2 = calloc(m, sizeof(uint32_t));    /* cut set of LP k-2 */
+    int last = 0;                                     /* the LP about to be solved is the last */
     int k;
     for (k = 0; k < o->malp_max; ++k) {
         int added = 0;
@@ -388,6 +394,19 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
             }
         }
         if (!added) break;
+        /* Theorem 2b rules out a recurring cut set: LP k equal to LP k-2 can only come from
+           an optimum that is not unique at the IPM's accuracy (the uniqueness the theorem
+           assumes), where a cut that bounds the optimum looks inactive. The steps are
+           deterministic, so the two LPs would then alternate until the cap. The decode ends
+           with the solution of the costlier of the two: u^(k-1) as it stands, or LP k (the
+           same LP as LP k-2) solved once more. */
+        if (o->cycle_stop && k >= 2 && !memcmp(mask, mask2, sizeof(uint32_t) * m)) {
+            s.status = -7;
+            if (cost_prev >= cost_prev2) break;
+            last = 1;
+        }
+        memcpy(mask2, mask1, sizeof(uint32_t) * m);
+        memcpy(mask1, mask, sizeof(uint32_t) * m);
         lp_t lp;
         lp_build(&lp, m, n, rowptr, col, gamma, mask);
         int its = 0;
@@ -426,7 +445,9 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
            beyond the IPM's accuracy (relative to 1 + c^T x, the scale of its gap test; c^T x
            = gamma^T u - gneg) means a cut was replaced or dropped while it still bound the
            optimum: the decode stops with a failure flag instead of cycling. */
+        if (last) break;
         if (cost < cost_prev - o->tau_cost * (1.0 + fabs(cost_prev - gneg))) { s.status = -5; break; }
+        cost_prev2 = cost_prev;
         cost_prev = cost;
     }
     if (k == o->malp_max && s.status == 0) s.status = -3;
@@ -453,7 +474,7 @@ int orc_decode(int m, int n, const int *rowptr, const int *col, const double *ga
     if (obj) *obj = g;
     if (u_out) memcpy(u_out, u, sizeof(double) * n);
     if (st) *st = s;
-    free(mask); free(active); free(u); free(nb); free(x); free(z); free(y);
+    free(mask); free(mask1); free(mask2); free(active); free(u); free(nb); free(x); free(z); free(y);
     return 0;
 }
 

@@ -30,7 +30,8 @@ class _Opts(C.Structure):
     _fields_ = [("malp_mode", C.c_int), ("malp_max", C.c_int), ("ipm_max", C.c_int),
                 ("tau_viol", C.c_double), ("tau_act", C.c_double), ("tau_int", C.c_double),
                 ("sigma_c", C.c_double), ("eta", C.c_double), ("eps", C.c_double),
-                ("eps_stall", C.c_double), ("tau_cost", C.c_double), ("box_clamp", C.c_int)]
+                ("eps_stall", C.c_double), ("tau_cost", C.c_double), ("box_clamp", C.c_int),
+                ("cycle_stop", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -52,11 +53,12 @@ class OracleOpts:
     eps_stall: float = 1e-7
     tau_cost: float = 1e-8
     box_clamp: int = 1
+    cycle_stop: int = 1
 
     def c(self) -> _Opts:
         return _Opts(self.malp_mode, self.malp_max, self.ipm_max, self.tau_viol, self.tau_act,
                      self.tau_int, self.sigma_c, self.eta, self.eps, self.eps_stall, self.tau_cost,
-                     self.box_clamp)
+                     self.box_clamp, self.cycle_stop)
 
 
 _lib = None

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblpdec.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT, FLAG_COST_DECREASE, FLAG_ALP_CAPACITY = \
-    -1, -2, -3, -4, -5, -6
+FLAG_IPM_CAP, FLAG_NONFINITE, FLAG_MALP_CAP, FLAG_INCONSISTENT, FLAG_COST_DECREASE, FLAG_ALP_CAPACITY, \
+    FLAG_CUT_CYCLE = -1, -2, -3, -4, -5, -6, -7
 
 OPT = {name: k for k, name in enumerate([
     "MALP_MODE", "PRECISION", "TAU_VIOL", "TAU_ACT", "TAU_INT", "IPM_EPS", "SIGMA", "ETA",

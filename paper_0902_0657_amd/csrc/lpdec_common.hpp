@@ -65,6 +65,7 @@ struct Plan {
     size_t u, g;                               // [n]
     size_t active;                             // u8 [m]
     size_t vprev;                              // u32 [m]: cut of each check in the previous LP
+    size_t vback;                              // u32 [m]: cut of each check two LPs back
     size_t cold_bytes;
 };
 
@@ -149,6 +150,7 @@ __host__ __device__ inline Plan make_plan(int m, int n, int dc, int dv, int pt_s
     p.g = o; o = lp_align(o + 8 * N);
     p.active = o; o = lp_align(o + M);
     p.vprev = o; o = lp_align(o + 4 * M);
+    p.vback = o; o = lp_align(o + 4 * M);
     p.cold_bytes = o;
     return p;
 }

@@ -454,6 +454,7 @@ struct Frame {
     double *ldsd;        // dense fallback: factor of the diagonal tile, reciprocals, vector block (LDS)
     uint8_t *active;
     uint32_t *vprev;     // cut of each check in the previous LP of this decode
+    uint32_t *vback;     // cut of each check in the LP before the previous one
     bool have_prev;      // an LP of this decode has been solved
     // level counts of the current preconditioner, LP rows
     int nlb, nlf, p;
@@ -492,6 +493,7 @@ struct Frame {
         for (int k = 0; k < 8; ++k) c64[k] = (double *)(cold + P.c64 + (size_t)k * lp_align(8 * (size_t)m));
         active = (uint8_t *)(cold + P.active);
         vprev = (uint32_t *)(cold + P.vprev);
+        vback = (uint32_t *)(cold + P.vback);
         have_prev = false;
     }
 
@@ -2227,10 +2229,12 @@ struct Frame {
             u[i] = g[i] >= 0.0 ? 0.0 : 1.0;   // hard decision
             if (g[i] < 0.0) gneg += g[i];
         }
-        for (int j = tid; j < m; j += nt) { vmask[j] = 0u; active[j] = 0; vprev[j] = 0u; }
+        for (int j = tid; j < m; j += nt) { vmask[j] = 0u; active[j] = 0; vprev[j] = 0u; vback[j] = 0u; }
         have_prev = false;
         gneg = block_sum1(gneg, sc);
-        double cost_prev = gneg;   // gamma^T u of the previous LP's solution
+        double cost_prev = gneg;    // gamma^T u of the previous LP's solution
+        double cost_prev2 = gneg;   // and of the one before
+        bool last = false;          // the LP about to be solved ends the decode
         int status = 0, k;
         for (k = 0; k < o.malp_max; ++k) {
             int added = 0;
@@ -2243,6 +2247,21 @@ struct Frame {
             }
             added = block_or(added, sc);
             if (!added) break;
+            // A cut set equal to that of two LPs back contradicts Theorem 2b; it comes from an
+            // optimum that is not unique at the IPM's accuracy, where a cut that bounds the
+            // optimum looks inactive. The steps are deterministic, so the two LPs would
+            // alternate until the cap: the decode ends with the solution of the costlier one,
+            // u^(k-1) as it stands or this LP (the same as LP k-2) solved once more.
+            if (k >= 2) {
+                int diff = 0;
+                for (int j = tid; j < m; j += nt) diff |= vmask[j] != vback[j];
+                if (!block_or(diff, sc)) {
+                    if (cost_prev >= cost_prev2) { status = LPDEC_FLAG_CUT_CYCLE; break; }
+                    last = true;
+                }
+            }
+            // vprev holds LP k-1's cuts until ipm() records this LP's
+            for (int j = tid; j < m; j += nt) vback[j] = vprev[j];
             if (a.trace && k < a.trace_cap)
                 for (int j = tid; j < m; j += nt) a.trace[((size_t)f * a.trace_cap + k) * m + j] = vmask[j];
             build_lists();
@@ -2268,6 +2287,7 @@ struct Frame {
             }
             cost = block_sum1(cost, sc);
             if (status < 0) break;
+            if (last) { status = LPDEC_FLAG_CUT_CYCLE; break; }
             // Theorem 2b: successive LP costs increase strictly. A decrease beyond the IPM's
             // accuracy (relative to 1 + c^T x, c^T x = gamma^T u - gneg) means a cut that still
             // bound the optimum was replaced or dropped; the decode ends with a failure flag
@@ -2275,6 +2295,7 @@ struct Frame {
                 status = LPDEC_FLAG_COST_DECREASE;
                 break;
             }
+            cost_prev2 = cost_prev;
             cost_prev = cost;
         }
         if (k == o.malp_max && status == 0) status = LPDEC_FLAG_MALP_CAP;

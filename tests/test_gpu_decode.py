@@ -202,6 +202,28 @@ def test_malp_cycle_frame(ctx, orc):
         _compare(orc, code, G, out, opts=orc.OracleOpts(malp_mode=mode))
 
 
+
+def test_malp_cut_cycle_frame(ctx, orc):
+    """The n=1024 frame at 1.99 dB whose LP optimum is flat along one cut at the IPM's
+    accuracy: MALP-A's cut sets alternate between two LPs that differ in the cut of check 96.
+    Both sides end the decode at the first recurrence (LPDEC_FLAG_CUT_CYCLE) with the costlier
+    LP's solution; MALP-B decodes it normally. The frame came from a serving run, where it ended
+    at the MALP cap before the recurrence test existed."""
+    import torch
+    from synth.channel import awgn_llr, frame_seed
+    code = regular_code(1024)
+    C = _code(ctx, code)
+    G = awgn_llr(code.n, 1.9857919617105901, 0.5, frame_seed(84, 1, 578))[None, :]
+    for mode, flag in ((0, -7), (1, 0)):
+        ctx.set_option("MALP_MODE", mode)
+        try:
+            out = ctx.decode_batch(C, cuda(G, torch.float64))
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option("MALP_MODE", 0)
+        assert host(out["flag"])[0] == flag
+        _compare(orc, code, G, out, opts=orc.OracleOpts(malp_mode=mode))
+
 def _sweep_oracle(args):
     import oracle as O
     n, mode, f = args

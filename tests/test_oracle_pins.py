@@ -666,14 +666,55 @@ def test_malp_cycle_frame_reaches_lp_optimum(orc):
         assert abs(res.objective - fun) <= 1e-6 * scale
         assert np.array_equal(res.xhat, (ustar > 0.5).astype(np.uint8))
         assert np.all(np.diff(res.trace_obj) > 0)          # Theorem 2b
-    # the planted mistake: no clamp. The cost check (Theorem 2b) ends the cycle at its first
-    # decrease; without the check the decode runs into the MALP cap
+    # the planted mistake: no clamp. The recurrence test ends the cycle when LP 2 repeats
+    # LP 0; the cost check (Theorem 2b) alone ends it at its first decrease; without either
+    # the decode runs into the MALP cap
     bad = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0), trace=True)
+    assert bad.flag == -7 and bad.malp_iters <= 4
+    bad = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0, cycle_stop=0), trace=True)
     assert bad.flag == -5 and bad.malp_iters <= 4
     assert bad.trace_obj[-1] < bad.trace_obj[-2]
-    worse = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0, tau_cost=1.0, malp_max=50))
+    worse = orc.decode(code, gamma, orc.OracleOpts(box_clamp=0, tau_cost=1.0, cycle_stop=0, malp_max=50))
     assert worse.flag == -3
 
+
+
+# A frame of the n=1024 (3,6) code at 1.99 dB whose MALP-A cut sets alternate between two LPs
+# that differ only in the cut of check 96 (odd sets 4 and 8). LP-A's optimum is unique but
+# flat along cut B: HiGHS finds LP-A points whose cost exceeds the optimum by 1e-9 and that
+# violate B by 6.9e-5, so the IPM's point (cost within its gap test) violates B by 2e-4, and
+# LP-B's point in turn violates A. Theorem 2 assumes unique optima; at the IPM's accuracy that
+# fails here, and both sides end the decode at the first recurrence of a cut set.
+FLAT_FRAME = dict(n=1024, ebn0=1.9857919617105901, seed=frame_seed(84, 1, 578))
+
+
+def test_malp_cut_cycle_ends_at_first_recurrence(orc):
+    code = regular_code(FLAT_FRAME["n"])
+    gamma = awgn_llr(code.n, FLAT_FRAME["ebn0"], 0.5, FLAT_FRAME["seed"])
+    fun, ustar = refs.feldman_lp(code, gamma)
+    scale = 1.0 + abs(fun - gamma[gamma < 0].sum())
+    res = orc.decode(code, gamma, orc.OracleOpts(), trace=True)
+    M = res.trace_mask
+    assert res.flag == -7 and res.malp_iters < 25
+    # the last LP solved is the one of two LPs back; the two LPs differ in one check's cut
+    assert np.array_equal(M[-1], M[-3]) and np.count_nonzero(M[-1] != M[-2]) == 1
+    # the output is the costlier LP's solution, optimal within the IPM's gap test
+    assert res.objective >= res.trace_obj[-2]
+    assert abs(res.objective - fun) <= 1e-6 * scale
+    fa, _ = refs.cutset_lp(code, gamma, M[-1])
+    fb, _ = refs.cutset_lp(code, gamma, M[-2])
+    assert abs(fa - fun) <= 1e-12 * scale and fun - 1e-6 * scale < fb < fun
+    # the decisions are those of the LP-decoding optimum; the point itself violates the other
+    # LP's cut by more than tau_viol
+    assert np.array_equal(res.xhat, (ustar > 0.5).astype(np.uint8))
+    assert 1e-4 < refs.max_parity_violation(code, res.u) < 1e-3
+    # MALP-B takes another path on this frame and ends normally (fractional output)
+    resb = orc.decode(code, gamma, orc.OracleOpts(malp_mode=1))
+    assert resb.flag == 0 and abs(resb.objective - fun) <= 1e-6 * scale
+    # the planted mistake: without the recurrence test the two LPs alternate up to the cap
+    bad = orc.decode(code, gamma, orc.OracleOpts(cycle_stop=0, malp_max=30), trace=True)
+    assert bad.flag == -3
+    assert all(np.array_equal(bad.trace_mask[k], bad.trace_mask[k - 2]) for k in range(20, 30))
 
 def _sweep_frame(args):
     import oracle as O
