@@ -1,11 +1,12 @@
 """Benchmark: LP-decoded frames/s of the batched decoder on the (3,6)-regular n=1024 code.
 
 One step = one launch of the decoder over a batch of 512 frames (Eb/N0 1.5 / 2.0 / 2.5 dB,
-171/171/170 frames, FP32 LLRs, FP32 PCG with FP64 refinement and FP64 interior-point
-iterations): every step of the hot path (cut search, cut update, interior-point iterations,
-triangular-set search, PCG) runs inside that launch. Inputs are resident in device memory
-before timing starts. Newton systems that PCG does not finish within its cap go to a dense
-FP64 Cholesky (the library's default); the method alone is the method_only leg.
+171/171/170 frames, FP32 LLRs, FP64 PCG vectors (--precision fp32: FP32 vectors) with FP64
+refinement and FP64 interior-point iterations): every step of the hot path (cut search, cut
+update, interior-point iterations, triangular-set search, PCG) runs inside that launch, and
+the steps run one after another. Inputs are resident in device memory before timing starts.
+Newton systems that PCG does not finish within its cap go to a dense FP64 Cholesky (the
+library's default); the method alone is the method_only leg.
 
 Prints one JSON line. Beside the main number:
   roofline        HBM bandwidth of the launch on the method's algorithmic bytes, with the
@@ -14,6 +15,8 @@ Prints one JSON line. Beside the main number:
                   per-frame decode times, decode statistics
   method_only     the same batch without the dense fallback (FP64 PCG, cap 2000)
   other_precision the same batch with the other PCG vector precision
+  overlapped      successive launches of the batch on three streams (one context each), so
+                  that a launch's last frames overlap the next launch's: sustained frames/s
   serving         Poisson arrivals of mixed-length frames through lpdec_server (persistent
                   engines, then the wave scheduler as serving_waves)
   plain_fp64      frames through lpdec_decode (FP64, one frame per launch, host pointers)
@@ -698,6 +701,46 @@ def run_leg(ctx, C, g, nf, dev, stream, steps=1, warmup=0, label=""):
     return out, step_ms, wall
 
 
+def overlapped_leg(code, G, dev, opts, ncu, ref, streams=3, launches=6):
+    """Launches of the same 512-frame batch issued in turn on `streams` streams, each with its
+    own context (workspace, outputs): a launch ends with its slowest frame, and meanwhile the
+    compute units its finished workgroups free take the next launch's frames. Reports the
+    sustained rate (launches x frames / wall time), each launch's duration (HIP events on its
+    stream) and whether every output equals the single-launch result."""
+    import torch
+    from paper_0902_0657_amd import Code, Context, stats_table
+    g = torch.as_tensor(G, device=dev)
+    nf = G.shape[0]
+    ctxs = [Context(0, **opts) for _ in range(streams)]
+    Cs = [Code.from_synth(c, code) for c in ctxs]
+    sts = [torch.cuda.Stream(dev) for _ in range(streams)]
+    outs = [ctxs[i].batch_outputs(Cs[i], nf, dev) for i in range(streams)]
+    for i in range(streams):
+        ctxs[i].decode_batch(Cs[i], g, out=outs[i], stream=sts[i])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    t0 = time.perf_counter()
+    for k in range(launches):
+        i = k % streams
+        ev[k][0].record(sts[i])
+        ctxs[i].decode_batch(Cs[i], g, out=outs[i], stream=sts[i])
+        ev[k][1].record(sts[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    same = all(np.array_equal(outs[i][key].cpu().numpy(), ref[key]) for i in range(streams) for key in ref)
+    busy = sum(float(stats_table(outs[i]["stats"])["ticks_total"].sum()) / 1e8 for i in range(streams))
+    for c in ctxs:
+        c.close()
+    log(f"overlapped: {launches} launches on {streams} streams in {wall:.2f} s")
+    return {"value": launches * nf / wall, "unit": "frames/s", "streams": streams, "launches": launches,
+            "frames_per_launch": nf, "wall_s": wall, "options": opts,
+            "launch_ms": {"p50": float(np.percentile(lat, 50)), "max": float(lat.max()),
+                          "note": "each launch from its start on its stream to its end (HIP events)"},
+            "cu_busy_fraction": busy / len(ctxs) * launches / (wall * ncu),
+            "same_results_as_single_launch": bool(same)}
+
+
 def leg_summary(name, ctx_opts, code, G, out, step_ms, ncu, elem, traffic=None, traffic_note=None):
     from paper_0902_0657_amd import stats_table
     st = stats_table(out["stats"])
@@ -877,6 +920,9 @@ def main():
             res[lname], *_ = leg_summary("c2", opts, code, G, ox, msx, ncu, 8 if opts["PRECISION"] == 1 else 4)
             log(f"{lname}: {msx.mean():.1f} ms")
             c2x.close()
+    if not args.no_legs:
+        ref = {"flag": flags, "xhat": xhat, "obj": objs}
+        res["overlapped"] = overlapped_leg(code, G, dev, main_opts, ncu, ref)
     for name in [c for c in args.configs.split(",") if c]:
         res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main", cpu=not args.no_cpu)
         log(f"config {name}: {res[f'config_{name}']['ms_per_step']:.0f} ms")
