@@ -1246,17 +1246,34 @@ struct Frame {
     static constexpr int kSmallLevel = 1 << 30;
     static constexpr int kOffMask = kSmallLevel - 1;
 
-    template <int G, typename T, typename GF, typename PF, typename FF>
-    LPD_INLINE void gsweep(const uint16_t *slots, const int *off, int nlev, GF gather, PF pre, FF finish)
+    //   A step gathers the value of its lane's entry from vec (with MASKED an index of m or
+    // above contributes 0; the header lane and lanes past the level gather a zero) and the
+    // header lane loads the row's own operands (pre, from the row index; other lanes load row
+    // 0's); only after all these loads are issued (a scheduling barrier keeps them together,
+    // so one wait covers them) are the signs applied, the operands combined (mid, off the
+    // path of the group sum), the group summed and the row finished.
+    template <int G, bool MASKED, typename T, typename V, typename PF, typename MF, typename FF>
+    LPD_INLINE void gsweep(const uint16_t *slots, const int *off, int nlev, const V *vec, PF pre, MF mid,
+                           FF finish)
     {
         if (nlev <= 0) return;
         const int g = tid / G, q = tid - g * G, ng = nt / G;
         const uint16_t zero = ben(Z, false);
         auto step = [&](bool valid, uint16_t e) {
-            const T v = gather(valid, e, q);
-            const auto pc = pre(valid && q == 0, e);
+            const int bi = b_idx(e);
+            const bool ok = valid && q != 0 && (!MASKED || bi < m);
+            const bool head = valid && q == 0;
+            // the row's operands first, the gather last: waiting for the gather then covers
+            // every load of the step
+            const auto pc = pre(head ? bi : 0);
+            T v = (T)vec[ok ? bi : (MASKED ? 0 : Z)];
+            __builtin_amdgcn_sched_barrier(0);
+            // unmasked, a lane without an entry has gathered the zero element: only the sign
+            // is applied
+            v = MASKED ? maskflip(v, b_neg(e), ok) : flip(v, b_neg(e));
+            const auto pm = mid(pc);   // the row's operands combined, beside the group sum
             const T sum = gsum<G>(v);
-            finish(valid && q == 0, e, pc, sum);
+            finish(head, e, pm, sum);
         };
         int L = 0, kA = 0, raw = off[0];
         uint16_t cur = !(raw & kSmallLevel) && g < (raw & kOffMask) ? slots[g * G + q] : zero;
@@ -1268,15 +1285,25 @@ struct Frame {
                     // the only dependent LDS access on the chain is the gather of a level
                     // (bounds are the same in every lane: readfirstlane keeps them in scalar
                     // registers, so the loop control is scalar)
-                    int l = L, a = kA, b = raw & kOffMask;
-                    uint16_t e = a + g < b ? slots[(a + g) * G + q] : zero;
-                    int raw1 = __builtin_amdgcn_readfirstlane(l + 1 < nlev ? off[l + 1] : 0);
+                    //   Every load of the loop is unconditional (a lane past its level reads
+                    // the level's first slot and its step is invalid; a bound past the last
+                    // level reads the last one and is not used), so the loop has no branches
+                    // around loads.
+                    const int nl = __builtin_amdgcn_readfirstlane(nlev);
+                    int l = __builtin_amdgcn_readfirstlane(L), a = __builtin_amdgcn_readfirstlane(kA);
+                    int b = __builtin_amdgcn_readfirstlane(raw & kOffMask);
+                    uint16_t e = slots[(a + g < b ? a + g : a) * G + q];
+                    int raw1 = __builtin_amdgcn_readfirstlane(off[l + 1 < nl ? l + 1 : l]);
+                    // nothing in flight on entry: the loop head then needs no wait for the
+                    // previous level's store
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
                     for (;;) {
-                        const bool more = (raw1 & kSmallLevel) != 0;
+                        const bool more = l + 1 < nl && (raw1 & kSmallLevel) != 0;
                         const int nb = raw1 & kOffMask;
-                        const uint16_t en = more && b + g < nb ? slots[(b + g) * G + q] : zero;
-                        const int raw2 = __builtin_amdgcn_readfirstlane(more && l + 2 < nlev ? off[l + 2] : 0);
+                        const uint16_t en = slots[(more && b + g < nb ? b + g : a) * G + q];
+                        const int raw2v = off[l + 2 < nl ? l + 2 : nl - 1];
                         step(a + g < b, e);
+                        const int raw2 = __builtin_amdgcn_readfirstlane(raw2v);
                         if (!more) break;
                         // the next level's gathers must see the level's stores. In LDS they do
                         // without a wait (the LDS executes one wave's instructions in issue
@@ -1321,14 +1348,10 @@ struct Frame {
     template <int G, typename T, typename UF>
     LPD_INLINE void back_sub_g(T *out, UF u_of_row)
     {
-        gsweep<G, T>(
-            bins, boff, nlb,
-            [&](bool valid, uint16_t e, int q) {
-                const int bi = b_idx(e);
-                const bool ok = valid && q != 0 && bi < m;
-                return maskflip((T)out[ok ? bi : 0], b_neg(e), ok);
-            },
-            [&](bool head, uint16_t e) { return (T)u_of_row(head ? b_idx(e) : 0); },
+        gsweep<G, true, T>(
+            bins, boff, nlb, out,
+            [&](int j) { return (T)u_of_row(j); },
+            [](T u0) { return u0; },
             [&](bool head, uint16_t e, T u0, T sum) {
                 if (head) {
                     const T acc = u0 + sum;
@@ -1347,14 +1370,10 @@ struct Frame {
     template <int G, typename T, typename EF>
     LPD_INLINE void fwd_sub_g(T *out, EF e_of_row)
     {
-        gsweep<G, T>(
-            fins, foff, nlf,
-            [&](bool valid, uint16_t e, int q) {
-                const int bi = b_idx(e);
-                const bool ok = valid && q != 0 && bi < m;
-                return maskflip((T)out[ok ? bi : 0], b_neg(e), ok);
-            },
-            [&](bool head, uint16_t e) { return (T)e_of_row(head ? b_idx(e) : 0); },
+        gsweep<G, true, T>(
+            fins, foff, nlf, out,
+            [&](int j) { return (T)e_of_row(j); },
+            [](T e0) { return e0; },
             [&](bool head, uint16_t e, T e0, T sum) {
                 if (head) {
                     const T acc = e0 + sum;
@@ -1418,19 +1437,16 @@ struct Frame {
         if (!(rr > (T)0)) return 0;
         const T stop = tol * tol * rr;
         T *const S = V.s;
+        struct HI { T h, i; };   // the row's h and 1/d of its paired column
         int it = 0;
         while (it < maxit) {
             // s = A_M^-T (D_M^-1 h)
-            gsweep<GF, T>(
-                fins, foff, nlf,
-                [&](bool valid, uint16_t e, int q) { return flip(S[valid && q ? b_idx(e) : Z], b_neg(e)); },
-                [&](bool head, uint16_t e) {
-                    const int j = head ? b_idx(e) : 0;
-                    const T e0 = V.h[j] * V.idm[j];
-                    pin(e0);
-                    return e0;
-                },
+            gsweep<GF, false, T>(
+                fins, foff, nlf, S,
+                [&](int j) { return HI{V.h[j], V.idm[j]}; },
+                [](HI hi) { return hi.h * hi.i; },
                 [&](bool head, uint16_t e, T e0, T sum) {
+#pragma clang fp contract(off)
                     if (head) {
                         const T acc = e0 + sum;
                         S[b_idx(e)] = b_neg(e) ? -acc : acc;
@@ -1447,17 +1463,10 @@ struct Frame {
             }
             __syncthreads();
             // f = A_M^-1 (A_N t) over s; l = h + D_M^-1 f
-            struct HI { T h, i; };
-            gsweep<GB, T>(
-                bins, boff, nlb,
-                [&](bool valid, uint16_t e, int q) { return flip(S[valid && q ? b_idx(e) : Z], b_neg(e)); },
-                [&](bool head, uint16_t e) {
-                    const int j = head ? b_idx(e) : 0;
-                    const HI hi{V.h[j], V.idm[j]};
-                    pin(hi.h);
-                    pin(hi.i);
-                    return hi;
-                },
+            gsweep<GB, false, T>(
+                bins, boff, nlb, S,
+                [&](int j) { return HI{V.h[j], V.idm[j]}; },
+                [](HI hi) { return hi; },
                 [&](bool head, uint16_t e, HI hi, T sum) {
                     if (head) {
                         const int j = b_idx(e);
