@@ -21,7 +21,8 @@ Prints one JSON line. Beside the main number:
                   engines, then the wave scheduler as serving_waves)
   plain_fp64      frames through lpdec_decode (FP64, one frame per launch, host pointers)
   cpu_baseline    the FP64 CPU oracle on the host cores, a time-bounded sample
-  config_c3/c4    (--configs c3,c4) one launch of the n=4096 / irregular n=8192 workloads
+  config_c3/c4    one launch of the n=4096 / irregular n=8192 workloads, with their rooflines
+                  and a time-bounded oracle sample (--no-configs leaves them out)
 """
 from __future__ import annotations
 
@@ -206,7 +207,7 @@ def cpu_baseline(name, frames, budget_s=20.0, max_workers=16):
             "host_cores": {"sched_getaffinity": avail, "lscpu": lscpu, "used": workers}}, done
 
 
-def cpu_sample_cutoff(name, frames, budget_s=90.0, max_workers=16):
+def cpu_sample_cutoff(name, frames, budget_s=75.0, max_workers=16):
     """The oracle on the host cores for the large workloads, whose frames take minutes each: one
     frame per worker process in index order, and every frame still running when the time
     budget ends is abandoned (the workers are terminated). Rate = frames finished / budget."""
@@ -600,7 +601,7 @@ def stored_traffic(name="c2"):
 
 
 PROFILE_COMMANDS = {
-    "c2": "python bench.py --steps 1 --warmup 0 --no-cpu --no-plain --no-legs --no-serve",
+    "c2": "python bench.py --steps 1 --warmup 0 --no-cpu --no-plain --no-legs --no-serve --no-configs",
     "c3": "python bench.py --only-configs --configs c3 --no-cpu",
     "c4": "python bench.py --only-configs --configs c4 --no-cpu",
 }
@@ -801,7 +802,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving legs")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving mix over n = 256, 1024, 4096 and the irregular 8192 code")
-    ap.add_argument("--configs", default="", help="comma list of extra whole-workload launches: c3, c4")
+    ap.add_argument("--configs", default="c3,c4",
+                    help="comma list of extra whole-workload launches (c3, c4)")
+    ap.add_argument("--no-configs", action="store_true", help="leave out the c3 / c4 launches")
     ap.add_argument("--summarize-profiles", default="",
                     help="DIR: write the profiles/ summaries from rocprofv3 output under DIR (no GPU)")
     ap.add_argument("--only-configs", action="store_true",
@@ -923,7 +926,7 @@ def main():
     if not args.no_legs:
         ref = {"flag": flags, "xhat": xhat, "obj": objs}
         res["overlapped"] = overlapped_leg(code, G, dev, main_opts, ncu, ref)
-    for name in [c for c in args.configs.split(",") if c]:
+    for name in [c for c in args.configs.split(",") if c and not args.no_configs]:
         res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main", cpu=not args.no_cpu)
         log(f"config {name}: {res[f'config_{name}']['ms_per_step']:.0f} ms")
     if not args.no_plain:
