@@ -179,7 +179,7 @@ def host_cores():
 def cpu_baseline(name, frames, budget_s=20.0, max_workers=16):
     """The FP64 CPU oracle on the host cores: one frame per worker process, frames taken in the
     given order until the time budget is used up (the frames in flight then finish). Workers:
-    the cores this process may run on, at most max_workers (a GPU machine's CPU share for one GPU)."""
+    the cores this process may run on, at most max_workers (the host CPU share of one GPU)."""
     from concurrent.futures import ProcessPoolExecutor, FIRST_COMPLETED, wait
     import oracle
     oracle.build(force=False)
@@ -625,7 +625,7 @@ def summarize_profiles(name, base):
         leg = bench[f"config_{name}"]
         roof = leg["roofline"]
     out = [f"# lpdec_main, {title}: rocprofv3 kernel statistics", "",
-           "Command (from the repository root, on the GPU box):", "",
+           "Command (from the repository root, on an MI355X):", "",
            f"    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_{name}_kt -o run -- {cmd}", "",
            "| kernel | calls | total ns | average ns | min ns | max ns | share % |", "|---|---|---|---|---|---|---|"]
     for r in stats:
@@ -652,7 +652,7 @@ def summarize_profiles(name, base):
     rec = {"traffic": {"sources_sha256": sources_digest(), "fetch_kib_per_launch": kib["fetch"][0],
                        "write_kib_per_launch": kib["write"][0], "fetch_scale": fs, "write_scale": ws,
                        "copy_fetch_kib": kib["fetch"][1], "copy_write_kib": kib["write"][1], "copy_bytes": copy_bytes}}
-    out = [f"# lpdec_main, {title}: HBM traffic counters", "", "Two counter runs (from the repository root, on the GPU box):", "",
+    out = [f"# lpdec_main, {title}: HBM traffic counters", "", "Two counter runs (from the repository root, on an MI355X):", "",
            f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_{name}_fetch -o run -- {cmd} --calib-copy",
            f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_{name}_write -o run -- {cmd} --calib-copy", "",
            "`--calib-copy` runs one 256 MiB device-to-device copy first; the counters of that copy",
