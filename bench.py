@@ -875,10 +875,20 @@ def main():
     g = torch.as_tensor(G, device=dev)
     stream = torch.cuda.current_stream(dev)
     nf = G.shape[0]
+    tune = None
+    c2_opts = dict(main_opts)
+    if not args.block:
+        # threads per frame picked by the launch-shape tuner on 128 frames of the batch
+        from paper_0902_0657_amd import autotune
+        tune = autotune.tune_block(ctx, C, g[interleaved_c2(128)].contiguous())
+        c2_opts["BLOCK"] = int(tune["block"])
+        log(f"autotune: BLOCK {tune['block']} ({', '.join(f'{b}: {t:.0f} ms' for b, t in tune['ms'].items())})")
     out, step_ms, wall = run_leg(ctx, C, g, nf, dev, stream, args.steps, args.warmup, "main")
     traffic, traffic_note = stored_traffic()
-    main_res, st, flags, xhat, objs = leg_summary("c2", main_opts, code, G, out, step_ms, ncu, 8 if fp64 else 4,
+    main_res, st, flags, xhat, objs = leg_summary("c2", c2_opts, code, G, out, step_ms, ncu, 8 if fp64 else 4,
                                                   traffic, traffic_note)
+    if tune is not None:
+        main_res["autotune"] = {"block": int(tune["block"]), "ms_on_128_frames": {str(b): float(t) for b, t in tune["ms"].items()}}
     value = main_res["value"]
     roof = main_res.pop("roofline")
     roof["kernel"] = f"lpdec_main<{'double' if fp64 else 'float'}, LDS, DECODE>"
@@ -925,7 +935,7 @@ def main():
             c2x.close()
     if not args.no_legs:
         ref = {"flag": flags, "xhat": xhat, "obj": objs}
-        res["overlapped"] = overlapped_leg(code, G, dev, main_opts, ncu, ref)
+        res["overlapped"] = overlapped_leg(code, G, dev, c2_opts, ncu, ref)
     for name in [c for c in args.configs.split(",") if c and not args.no_configs]:
         res[f"config_{name}"] = config_leg(name, dev, stream, main_opts, "main", cpu=not args.no_cpu)
         log(f"config {name}: {res[f'config_{name}']['ms_per_step']:.0f} ms")
