@@ -1238,9 +1238,9 @@ struct Frame {
     // finish needs (pre), the group sums the values with DPP, and the header lane finishes
     // the row. Levels are separated by a barrier; level bounds are read two levels ahead and
     // each lane's entry of the next level one level ahead.
-    //   A level with at most 64 / G slots fits one pass of wave 0. A run of such levels (the
-    // long dependency chains of late interior-point iterations are mostly single rows) is
-    // swept by wave 0 alone: its LDS accesses are processed in program order, so a level
+    //   A level with at most 64 / G slots fits one pass of wave 0. A run of such levels (most
+    // levels of the long dependency chains of late interior-point iterations hold a few rows)
+    // is swept by wave 0 alone: its LDS accesses are processed in program order, so a level
     // needs only the wait for the previous level's stores, not a workgroup barrier; the other
     // waves meet wave 0 at the end of the run. build_levels() marks such levels in off[].
     static constexpr int kSmallLevel = 1 << 30;
