@@ -601,7 +601,7 @@ def stored_traffic(name="c2"):
 
 
 PROFILE_COMMANDS = {
-    "c2": "python bench.py --steps 1 --warmup 0 --no-cpu --no-plain --no-legs --no-serve --no-configs",
+    "c2": "python bench.py --steps 1 --warmup 0 --no-cpu --no-plain --no-legs --no-serve --no-configs --block 256",
     "c3": "python bench.py --only-configs --configs c3 --no-cpu",
     "c4": "python bench.py --only-configs --configs c4 --no-cpu",
 }
