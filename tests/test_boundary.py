@@ -40,3 +40,23 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
         finally:
             _lib._lib = None
+
+
+def test_argument_errors_are_reported_before_any_device_work():
+    """Null handles and invalid devices come back as LPDEC_EINVAL / LPDEC_EDEVICE from the C ABI
+    itself (runs on a host without a GPU: these paths check their arguments first)."""
+    import ctypes as C
+    from paper_0902_0657_amd import _lib
+    L = _lib.load()
+    p = C.c_void_p()
+    assert L.lpdec_ctx_create(0, None) == _lib.EINVAL
+    assert L.lpdec_ctx_create(-1, C.byref(p)) == _lib.EDEVICE and not p.value
+    assert L.lpdec_ctx_destroy(None) == _lib.EINVAL
+    assert L.lpdec_set_option(None, _lib.OPT["PRECISION"], 1.0) == _lib.EINVAL
+    v = C.c_double()
+    assert L.lpdec_get_option(None, _lib.OPT["PRECISION"], C.byref(v)) == _lib.EINVAL
+    assert L.lpdec_code_destroy(None) == _lib.EINVAL
+    assert L.lpdec_decode_batch(None, None, 1, None, 0, None, None, None, None, None, None) == _lib.EINVAL
+    assert L.lpdec_server_poll(None, 0, None, None, None, None) == _lib.EINVAL
+    assert L.lpdec_server_destroy(None) == _lib.EINVAL
+    assert L.lpdec_last_error(None) == b"null context"
