@@ -130,7 +130,7 @@ const char *lpdec_last_error(const lpdec_ctx *ctx);
  *                  5 = from Algorithm 6 (incremental greedy search with the Triangulation Step
  *                  of Algorithm 5; O(q^2) work per search, blocks of columns tested at once)
  *   XI_TOL         inside the IPM a Newton solve is accurate enough once its residual
- *                  perturbs the complementarity equation by at most XI_TOL * mu (0.3)
+ *                  perturbs the complementarity equation by at most XI_TOL * mu (0.9)
  *   DIRECT_FALLBACK 1 (default) = a Newton solve whose PCG rounds end without meeting the
  *                  XI_TOL goal is solved again by a dense Cholesky factorisation of
  *                  A D^2 A^T on the GPU (FP64 matrix cores, in the frame's global workspace,

@@ -124,7 +124,7 @@ void default_opts(lpdec::Opts &o)
     o.eta = 0.9995;
     o.pcg_tol = 1e-6;
     o.ref_tol = 1e-10;
-    o.xi_tol = 0.3;
+    o.xi_tol = 0.9;
 }
 
 lpdec::CodeView view(const lpdec_code *c)
